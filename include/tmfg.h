@@ -1,0 +1,154 @@
+/*
+ * tmfg.h -- C ABI of libtmfg: triangular maximally filtered graph (TMFG) construction
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * The method is the TMFG of Raphael & Shun, "Faster Parallel Triangular Maximally
+ * Filtered Graphs and Hierarchical Clustering" (arXiv 2408.09399): from an n x n
+ * similarity matrix S (Section 2: S[i,j] is the weight of edge (i,j); Section 5: S is
+ * the Pearson correlation of n time series) build a planar graph by starting from a
+ * 4-clique and repeatedly joining one uninserted vertex to the three corners of one
+ * triangular face, choosing the face/vertex pair whose three new edges have the largest
+ * weight sum (the gain). Algorithms 1 and 2 give the set-up: four seed vertices of
+ * largest row sum, one up-front sort of every row of S, then the insertion loop.
+ *
+ * Readings this library takes where the paper is silent:
+ *   - seed score of v: sum over u != v of S[v][u], float64, added in index order of u;
+ *     seed v1..v4 = the four largest by (score desc, id asc), in that order;
+ *   - gain of face {a < b < c} and vertex u: float32 ((S[a][u] + S[b][u]) + S[c][u]);
+ *   - each step takes the largest gain over all (live face, uninserted vertex) pairs; ties
+ *     go to the lowest face id, then the lowest vertex id (this is the exact greedy rule of
+ *     the sequential TMFG, Section 2; the paper's candidate heuristic is not used);
+ *   - the split face f = {x < y < z} with new vertex u keeps id f as sorted(u,x,y);
+ *     sorted(u,y,z) and sorted(u,x,z) take the next two ids;
+ *   - the per-vertex sort orders u != v by (S[v][u] desc, u asc), -0.0 equal to +0.0.
+ *
+ * Conventions
+ *   - All ids are 0-based int32. All data pointers are DEVICE pointers (hipMalloc or
+ *     torch CUDA tensors on the plan's device) owned by the caller, unless stated.
+ *   - Matrices are row-major, densely packed (row stride = number of columns).
+ *   - Calls that take a stream only enqueue work on it and return at once; results are
+ *     valid after the stream has been synchronised.
+ *   - Argument errors are returned synchronously, before any GPU work is enqueued.
+ *     Errors found on the device (non-finite input, asymmetric W, a constant series) are
+ *     written as a tmfg_status to the caller's device status word; the other outputs of
+ *     that call are then undefined. A failing HIP call returns TMFG_E_HIP; its raw
+ *     hipError_t is available from tmfg_last_hip_error() on the same host thread.
+ *   - A plan is not thread-safe: use one plan per host thread. Calls that share a plan
+ *     must be ordered on one stream, since they share the plan's scratch memory.
+ *   - Limits: 4 <= n <= 20480 (rows are sorted inside one workgroup's 160 KB LDS and ids
+ *     are stored in 16 bits); 2 <= L.
+ */
+#ifndef TMFG_H_
+#define TMFG_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TMFG_OK = 0,
+  TMFG_E_INVALID = 1,     /* null pointer, both or neither of X and W, bad flags, misaligned buffer */
+  TMFG_E_SIZE = 2,        /* n < 4, n > n_max (or > 20480), L < 2, L > L_max */
+  TMFG_E_NONFINITE = 3,   /* NaN or Inf in X or W (device-detected) */
+  TMFG_E_ASYMMETRIC = 4,  /* W[i][j] and W[j][i] differ in their bits (device-detected) */
+  TMFG_E_DEGENERATE = 5,  /* a series with all values equal: no Pearson correlation */
+  TMFG_E_NOMEM = 6,       /* device allocation failed */
+  TMFG_E_HIP = 7,         /* a HIP runtime call failed; see tmfg_last_hip_error() */
+  TMFG_E_INTERNAL = 8     /* an internal consistency check failed on the device */
+} tmfg_status;
+
+/* Plan flags. */
+enum {
+  TMFG_NO_VALIDATE = 1u << 0, /* skip the finite / bitwise-symmetry check of a caller W */
+  TMFG_TIMING = 1u << 1       /* record per-phase HIP events (tmfg_plan_phase_ms) */
+};
+
+typedef struct tmfg_plan_s* tmfg_plan;
+
+/* One TMFG construction. Exactly one of X and W is non-NULL. */
+typedef struct {
+  int32_t n;            /* number of vertices (series) */
+  int32_t L;            /* series length; ignored when X is NULL */
+  const float* X;       /* n x L series, or NULL */
+  const float* W;       /* n x n similarity, finite and bitwise symmetric, or NULL */
+  float* W_out;         /* optional n x n: the float32 similarity the build used */
+  int32_t* order;       /* n: v1..v4 (seed rank order), then vertices in insertion order */
+  int32_t* edges;       /* (3n-6) x 2: (v1,v2),(v1,v3),(v1,v4),(v2,v3),(v2,v4),(v3,v4),
+                           then (u,x),(u,y),(u,z) for each step */
+  int32_t* steps;       /* (n-4) x 4: face id f, corners x < y < z joined at each step
+                           (may be NULL when n == 4) */
+  float* step_gain;     /* n-4: float32 gain of each step (may be NULL when n == 4) */
+  int32_t* faces;       /* (2n-4) x 3: final faces, ascending corner triples, by face id */
+  int32_t* status;      /* 1: tmfg_status of the build, written last */
+} tmfg_job;
+
+/* Create a plan for builds with n <= n_max and L <= L_max on the current HIP device.
+   Allocates the scratch (similarity matrix, standardised series, sorted ids, face
+   records; see tmfg_footprint_bytes). */
+tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags);
+
+/* Release a plan and its scratch. Waits for the plan's outstanding work. NULL is a no-op. */
+tmfg_status tmfg_plan_destroy(tmfg_plan plan);
+
+/* Device bytes a plan for (n_max, L_max) holds. */
+size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags);
+
+/* Build one TMFG (Pearson similarity if X is given, the per-vertex sort, the seed and
+   the n-4 insertions) asynchronously on `stream`. */
+tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream);
+
+/* Per-phase milliseconds of the plan's last build made with TMFG_TIMING: [0] similarity
+   (or validation of a caller W), [1] seed scores, [2] row sort, [3] insertion loop
+   (seed selection, initial faces and the n-4 steps), [4] total. Synchronises on the
+   last event. */
+tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
+
+/* Counters of the plan's last build (synchronous copy): [0] stale face recomputes,
+   [1] walk rounds, [2] full-row sweeps, [3] selection phases. */
+tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[4]);
+
+/* ---- The stages of a build, callable on their own ------------------------------- */
+
+/* Pearson similarity of n series of length L (paper, Section 5, Datasets):
+   W[i][j] = <z_i, z_j> with z = (x - mean) / ||x - mean||, float32 via FP32 MFMA.
+   W is bitwise symmetric with an exact 1.0f diagonal, clamped to [-1, 1], no -0.0.
+   *status receives TMFG_OK, TMFG_E_NONFINITE or TMFG_E_DEGENERATE. */
+tmfg_status tmfg_correlation(tmfg_plan plan, const float* X, int32_t n, int32_t L, float* W,
+                             int32_t* status, hipStream_t stream);
+
+/* Per-vertex order (Algorithm 1, sort of each row of S): idx[v*ld + k], k < n-1, is the
+   k-th vertex u != v by (W[v][u] desc, u asc), as uint16. ld must be a multiple of 8 and
+   at least n-1 rounded up to 8; idx must be 16-byte aligned; entries n-1..ld-1 of each
+   row are overwritten with 0xffff up to the next multiple of 8. */
+tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, int64_t ld,
+                           hipStream_t stream);
+
+/* Seed (Algorithms 1 and 2, first comment): scores[v] = float64 sum of W[v][u] over
+   u != v in index order; seed4 = the four largest by (score desc, id asc). W must be
+   bitwise symmetric (column sums are used). */
+tmfg_status tmfg_seed(tmfg_plan plan, const float* W, int32_t n, double* scores, int32_t* seed4,
+                      hipStream_t stream);
+
+/* Exact best vertex of each face (the per-face rule of Section 2 / Section 4.1's
+   orig-tmfg): for face f with corners faces[3f..3f+2] (any order), best_u[f] = the
+   vertex u with bit u clear in `inserted` (ceil(n/32) words, bit u of word u/32)
+   maximising the float32 gain, lowest u on ties, and best_gain[f] its gain; -1 and
+   -inf when every vertex is marked. Reads three full rows of W per face. */
+tmfg_status tmfg_face_sweep(tmfg_plan plan, const float* W, int32_t n, const int32_t* faces,
+                            int32_t nfaces, const uint32_t* inserted, int32_t* best_u,
+                            float* best_gain, hipStream_t stream);
+
+/* ---- Diagnostics ------------------------------------------------------------------ */
+
+const char* tmfg_status_string(tmfg_status s);
+int tmfg_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TMFG_H_ */

@@ -1,0 +1,280 @@
+"""ctypes binding of libtmfg (argument marshalling only; every step runs in the HIP kernels).
+
+Tensors passed in must be CUDA (ROCm) tensors on the plan's device, contiguous, of the
+dtype named in the C header include/tmfg.h. PyTorch is used for device memory and
+streams only. If libtmfg.so has not been built the first call raises at once: there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtmfg.so")
+
+STATUS = {
+    0: "TMFG_OK", 1: "TMFG_E_INVALID", 2: "TMFG_E_SIZE", 3: "TMFG_E_NONFINITE",
+    4: "TMFG_E_ASYMMETRIC", 5: "TMFG_E_DEGENERATE", 6: "TMFG_E_NOMEM", 7: "TMFG_E_HIP",
+    8: "TMFG_E_INTERNAL",
+}
+NO_VALIDATE = 1 << 0
+TIMING = 1 << 1
+
+# Every symbol the header declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_I = ctypes.c_int32
+SIGNATURES = {
+    "tmfg_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, ctypes.c_uint32]),
+    "tmfg_plan_destroy": (_I, [_P]),
+    "tmfg_footprint_bytes": (ctypes.c_size_t, [_I, _I, ctypes.c_uint32]),
+    "tmfg_build": (_I, [_P, _P, _P]),
+    "tmfg_plan_phase_ms": (_I, [_P, ctypes.POINTER(ctypes.c_float)]),
+    "tmfg_plan_stats": (_I, [_P, ctypes.POINTER(_I)]),
+    "tmfg_correlation": (_I, [_P, _P, _I, _I, _P, _P, _P]),
+    "tmfg_sort_rows": (_I, [_P, _P, _I, _P, ctypes.c_int64, _P]),
+    "tmfg_seed": (_I, [_P, _P, _I, _P, _P, _P]),
+    "tmfg_face_sweep": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P]),
+    "tmfg_status_string": (ctypes.c_char_p, [_I]),
+    "tmfg_last_hip_error": (ctypes.c_int, []),
+}
+
+
+class TmfgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = int(code)
+        name = STATUS.get(self.code, str(code))
+        msg = f"{where}: {name}"
+        if self.code == 7:
+            msg += f" (hipError {_lib().tmfg_last_hip_error()})"
+        super().__init__(msg)
+
+
+class Job(ctypes.Structure):
+    _fields_ = [
+        ("n", _I), ("L", _I), ("X", _P), ("W", _P), ("W_out", _P), ("order", _P),
+        ("edges", _P), ("steps", _P), ("step_gain", _P), ("faces", _P), ("status", _P),
+    ]
+
+
+_LIB: Optional[ctypes.CDLL] = None
+
+
+def _lib() -> ctypes.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2408_09399_amd.build` (no CPU fallback exists)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def lib() -> ctypes.CDLL:
+    return _lib()
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise TmfgError(code, where)
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _need(t, dtype, name: str):
+    import torch
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def footprint_bytes(n_max: int, L_max: int, flags: int = 0) -> int:
+    return int(_lib().tmfg_footprint_bytes(n_max, L_max, flags))
+
+
+class Plan:
+    """A plan owns the scratch for builds with n <= n_max and L <= L_max."""
+
+    def __init__(self, n_max: int, L_max: int = 2, flags: int = 0):
+        h = ctypes.c_void_p()
+        _check(_lib().tmfg_plan_create(ctypes.byref(h), n_max, L_max, flags), "tmfg_plan_create")
+        self._h = h
+        self.n_max, self.L_max, self.flags = n_max, L_max, flags
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _check(_lib().tmfg_plan_destroy(self._h), "tmfg_plan_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def phase_ms(self) -> Tuple[float, ...]:
+        out = (ctypes.c_float * 5)()
+        _check(_lib().tmfg_plan_phase_ms(self.handle, out), "tmfg_plan_phase_ms")
+        return tuple(float(x) for x in out)
+
+    def stats(self) -> Tuple[int, ...]:
+        out = (ctypes.c_int32 * 4)()
+        _check(_lib().tmfg_plan_stats(self.handle, out), "tmfg_plan_stats")
+        return tuple(int(x) for x in out)
+
+
+@dataclasses.dataclass
+class Result:
+    order: "object"
+    edges: "object"
+    steps: "object"
+    step_gain: "object"
+    faces: "object"
+    status: "object"
+    W: "object" = None
+
+    def to_numpy(self) -> dict:
+        d = {k: getattr(self, k).cpu().numpy() for k in ("order", "edges", "steps", "step_gain", "faces")}
+        d["status"] = int(self.status.item())
+        if self.W is not None:
+            d["W"] = self.W.cpu().numpy()
+        return d
+
+
+def alloc_result(n: int, device, keep_w: bool = False) -> Result:
+    import torch
+    i32 = dict(dtype=torch.int32, device=device)
+    return Result(
+        order=torch.empty(n, **i32),
+        edges=torch.empty((3 * n - 6, 2), **i32),
+        steps=torch.empty((max(n - 4, 0), 4), **i32),
+        step_gain=torch.empty(max(n - 4, 0), dtype=torch.float32, device=device),
+        faces=torch.empty((2 * n - 4, 3), **i32),
+        status=torch.full((1,), -1, **i32),
+        W=torch.empty((n, n), dtype=torch.float32, device=device) if keep_w else None,
+    )
+
+
+def make_job(n: int, L: int, X, W, res: Result) -> Job:
+    j = Job()
+    j.n, j.L = n, L
+    j.X, j.W = _ptr(X), _ptr(W)
+    j.W_out = _ptr(res.W)
+    j.order, j.edges = _ptr(res.order), _ptr(res.edges)
+    j.steps = _ptr(res.steps) if n > 4 else None
+    j.step_gain = _ptr(res.step_gain) if n > 4 else None
+    j.faces, j.status = _ptr(res.faces), _ptr(res.status)
+    return j
+
+
+def build(X=None, W=None, plan: Optional[Plan] = None, stream=None, keep_w: bool = False,
+          out: Optional[Result] = None) -> Result:
+    """Enqueue one TMFG build (from series X (n, L) or similarity W (n, n), float32)."""
+    import torch
+    if (X is None) == (W is None):
+        raise ValueError("give exactly one of X and W")
+    src = _need(X if X is not None else W, torch.float32, "X" if X is not None else "W")
+    n = src.shape[0]
+    L = src.shape[1] if X is not None else 0
+    if plan is None:
+        plan = Plan(n, max(L, 2))
+    res = out if out is not None else alloc_result(n, src.device, keep_w)
+    job = make_job(n, L, X, W, res)
+    _check(_lib().tmfg_build(plan.handle, ctypes.byref(job), _stream(stream)), "tmfg_build")
+    res._plan = plan          # keep the scratch alive until the caller drops the result
+    return res
+
+
+def correlation(X, plan: Optional[Plan] = None, stream=None):
+    """Pearson similarity (float32, MFMA). Returns (W, status tensor)."""
+    import torch
+    X = _need(X, torch.float32, "X")
+    n, L = X.shape
+    if plan is None:
+        plan = Plan(n, L)
+    W = torch.empty((n, n), dtype=torch.float32, device=X.device)
+    status = torch.full((1,), -1, dtype=torch.int32, device=X.device)
+    _check(_lib().tmfg_correlation(plan.handle, _ptr(X), n, L, _ptr(W), _ptr(status), _stream(stream)),
+           "tmfg_correlation")
+    return W, status
+
+
+def sort_stride(n: int) -> int:
+    return (max(n - 1, 1) + 7) // 8 * 8
+
+
+def sort_rows(W, plan: Optional[Plan] = None, stream=None):
+    """Per-vertex order as an (n, ld) int16 tensor holding uint16 ids (first n-1 valid)."""
+    import torch
+    W = _need(W, torch.float32, "W")
+    n = W.shape[0]
+    if plan is None:
+        plan = Plan(n, 2)
+    ld = sort_stride(n)
+    idx = torch.empty((n, ld), dtype=torch.int16, device=W.device)
+    _check(_lib().tmfg_sort_rows(plan.handle, _ptr(W), n, _ptr(idx), ld, _stream(stream)), "tmfg_sort_rows")
+    return idx
+
+
+def seed(W, plan: Optional[Plan] = None, stream=None):
+    """Seed scores (float64) and the four seed vertices."""
+    import torch
+    W = _need(W, torch.float32, "W")
+    n = W.shape[0]
+    if plan is None:
+        plan = Plan(n, 2)
+    scores = torch.empty(n, dtype=torch.float64, device=W.device)
+    s4 = torch.empty(4, dtype=torch.int32, device=W.device)
+    _check(_lib().tmfg_seed(plan.handle, _ptr(W), n, _ptr(scores), _ptr(s4), _stream(stream)), "tmfg_seed")
+    return scores, s4
+
+
+def face_sweep(W, faces, inserted_words, plan: Optional[Plan] = None, stream=None):
+    """Exact best vertex per face by a full sweep. faces: (F, 3) int32; inserted: int32 words."""
+    import torch
+    W = _need(W, torch.float32, "W")
+    faces = _need(faces, torch.int32, "faces")
+    inserted_words = _need(inserted_words, torch.int32, "inserted")
+    n = W.shape[0]
+    if plan is None:
+        plan = Plan(n, 2)
+    F = faces.shape[0]
+    bu = torch.empty(F, dtype=torch.int32, device=W.device)
+    bg = torch.empty(F, dtype=torch.float32, device=W.device)
+    _check(_lib().tmfg_face_sweep(plan.handle, _ptr(W), n, _ptr(faces), F, _ptr(inserted_words),
+                                  _ptr(bu), _ptr(bg), _stream(stream)), "tmfg_face_sweep")
+    return bu, bg

@@ -1,0 +1,288 @@
+// libtmfg C ABI: plans, scratch memory and the build pipeline.
+#include "../../include/tmfg.h"
+#include "common.h"
+#include "internal.h"
+
+#include <new>
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+tmfg_status hip_fail(hipError_t e) {
+  g_last_hip = (int)e;
+  return TMFG_E_HIP;
+}
+#define TMFG_HIP(call)                       \
+  do {                                       \
+    hipError_t e_ = (call);                  \
+    if (e_ != hipSuccess) return hip_fail(e_); \
+  } while (0)
+
+constexpr int kPhaseEvents = 5;
+
+__global__ void reset_flags_kernel(uint32_t* flags) { *flags = 0; }
+
+// Turn device error flags into a status word (for stage entry points).
+__global__ void flags_to_status_kernel(const uint32_t* flags, int32_t* status) {
+  const uint32_t f = *flags;
+  *status = (f & tmfg::kFlagNonFinite) ? TMFG_E_NONFINITE
+          : (f & tmfg::kFlagAsymmetric) ? TMFG_E_ASYMMETRIC
+          : (f & tmfg::kFlagDegenerate) ? TMFG_E_DEGENERATE
+          : f ? TMFG_E_INTERNAL : TMFG_OK;
+}
+
+struct Sizes {
+  int n, L;
+  int n_pad, L_pad;
+  int64_t ldi;
+  size_t z_bytes, w_bytes, idx_bytes, scores_bytes, frec_bytes;
+};
+
+Sizes sizes_for(int n, int L) {
+  Sizes s;
+  s.n = n;
+  s.L = L;
+  s.n_pad = (int)tmfg::round_up(n, tmfg::corr_row_pad());
+  s.L_pad = (int)tmfg::round_up(L < 2 ? 2 : L, tmfg::corr_k_pad());
+  s.ldi = tmfg::sort_row_stride(n);
+  s.z_bytes = (size_t)s.n_pad * s.L_pad * sizeof(float);
+  s.w_bytes = (size_t)n * n * sizeof(float);
+  s.idx_bytes = (size_t)n * s.ldi * sizeof(uint16_t);
+  s.scores_bytes = (size_t)n * sizeof(double);
+  s.frec_bytes = (size_t)(2 * n - 4) * 16;
+  return s;
+}
+
+}  // namespace
+
+struct tmfg_plan_s {
+  int device = 0;
+  int n_max = 0, L_max = 0;
+  uint32_t flags = 0;
+  Sizes sz{};
+  float* Z = nullptr;
+  float* W = nullptr;
+  uint16_t* idx = nullptr;
+  double* scores = nullptr;
+  uint4* frec = nullptr;
+  uint32_t* dflags = nullptr;
+  int32_t* stats = nullptr;
+  hipEvent_t ev[kPhaseEvents] = {};
+  bool timed = false;
+};
+
+namespace {
+
+void plan_free(tmfg_plan p) {
+  if (!p) return;
+  hipFree(p->Z);
+  hipFree(p->W);
+  hipFree(p->idx);
+  hipFree(p->scores);
+  hipFree(p->frec);
+  hipFree(p->dflags);
+  hipFree(p->stats);
+  for (auto& e : p->ev)
+    if (e) hipEventDestroy(e);
+  delete p;
+}
+
+tmfg_status alloc(void** ptr, size_t bytes) {
+  hipError_t e = hipMalloc(ptr, bytes < 256 ? 256 : bytes);
+  if (e == hipErrorOutOfMemory) {
+    g_last_hip = (int)e;
+    return TMFG_E_NOMEM;
+  }
+  if (e != hipSuccess) return hip_fail(e);
+  return TMFG_OK;
+}
+
+bool valid_n(int n, int n_max) { return n >= tmfg::kMinN && n <= n_max && n <= tmfg::kMaxN; }
+
+void record(tmfg_plan p, int i, hipStream_t s) {
+  if (p->flags & TMFG_TIMING) hipEventRecord(p->ev[i], s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tmfg_status_string(tmfg_status s) {
+  switch (s) {
+    case TMFG_OK: return "ok";
+    case TMFG_E_INVALID: return "invalid argument";
+    case TMFG_E_SIZE: return "size out of range";
+    case TMFG_E_NONFINITE: return "non-finite input";
+    case TMFG_E_ASYMMETRIC: return "similarity matrix not bitwise symmetric";
+    case TMFG_E_DEGENERATE: return "series with zero variance";
+    case TMFG_E_NOMEM: return "out of device memory";
+    case TMFG_E_HIP: return "HIP runtime error";
+    case TMFG_E_INTERNAL: return "internal error";
+  }
+  return "unknown status";
+}
+
+int tmfg_last_hip_error(void) { return g_last_hip; }
+
+size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags) {
+  (void)flags;
+  if (n_max < tmfg::kMinN) return 0;
+  const Sizes s = sizes_for(n_max, L_max);
+  return s.z_bytes + s.w_bytes + s.idx_bytes + s.scores_bytes + s.frec_bytes + 256 * 2;
+}
+
+tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags) {
+  if (!plan) return TMFG_E_INVALID;
+  *plan = nullptr;
+  if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING)) return TMFG_E_INVALID;
+  if (n_max < tmfg::kMinN || n_max > tmfg::kMaxN || L_max < 2) return TMFG_E_SIZE;
+  tmfg_plan p = new (std::nothrow) tmfg_plan_s();
+  if (!p) return TMFG_E_NOMEM;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) {
+    delete p;
+    return hip_fail(e);
+  }
+  p->n_max = n_max;
+  p->L_max = L_max;
+  p->flags = flags;
+  p->sz = sizes_for(n_max, L_max);
+  tmfg_status st;
+  if ((st = alloc((void**)&p->Z, p->sz.z_bytes)) != TMFG_OK ||
+      (st = alloc((void**)&p->W, p->sz.w_bytes)) != TMFG_OK ||
+      (st = alloc((void**)&p->idx, p->sz.idx_bytes)) != TMFG_OK ||
+      (st = alloc((void**)&p->scores, p->sz.scores_bytes)) != TMFG_OK ||
+      (st = alloc((void**)&p->frec, p->sz.frec_bytes)) != TMFG_OK ||
+      (st = alloc((void**)&p->dflags, 4)) != TMFG_OK || (st = alloc((void**)&p->stats, 16)) != TMFG_OK) {
+    plan_free(p);
+    return st;
+  }
+  for (auto& ev : p->ev) {
+    e = hipEventCreate(&ev);
+    if (e != hipSuccess) {
+      plan_free(p);
+      return hip_fail(e);
+    }
+  }
+  *plan = p;
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_plan_destroy(tmfg_plan plan) {
+  if (!plan) return TMFG_OK;
+  hipError_t e = hipDeviceSynchronize();
+  plan_free(plan);
+  if (e != hipSuccess) return hip_fail(e);
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) {
+  if (!plan || !job) return TMFG_E_INVALID;
+  const int n = job->n;
+  if ((job->X == nullptr) == (job->W == nullptr)) return TMFG_E_INVALID;
+  if (!job->order || !job->edges || !job->faces || !job->status) return TMFG_E_INVALID;
+  if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
+  if (n > 4 && (!job->steps || !job->step_gain)) return TMFG_E_INVALID;
+  if (job->X && (job->L < 2 || job->L > plan->L_max)) return TMFG_E_SIZE;
+
+  record(plan, 0, stream);
+  hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(1), 0, stream, plan->dflags);
+  TMFG_HIP(hipGetLastError());
+  const float* Wt;
+  if (job->X) {
+    const Sizes s = sizes_for(n, job->L);
+    float* Wdst = job->W_out ? job->W_out : plan->W;
+    TMFG_HIP(tmfg::launch_standardize(job->X, n, job->L, plan->Z, s.n_pad, s.L_pad, plan->dflags, stream));
+    TMFG_HIP(tmfg::launch_corr_gemm(plan->Z, n, s.L_pad, Wdst, stream));
+    Wt = Wdst;
+  } else {
+    if (!(plan->flags & TMFG_NO_VALIDATE)) TMFG_HIP(tmfg::launch_validate(job->W, n, plan->dflags, stream));
+    if (job->W_out)
+      TMFG_HIP(hipMemcpyAsync(job->W_out, job->W, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    Wt = job->W;
+  }
+  record(plan, 1, stream);
+  TMFG_HIP(tmfg::launch_seed_scores(Wt, n, plan->scores, stream));
+  record(plan, 2, stream);
+  const int64_t ldi = tmfg::sort_row_stride(n);
+  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, plan->idx, ldi, stream));
+  record(plan, 3, stream);
+  tmfg::LoopParams P{};
+  P.W = Wt;
+  P.n = n;
+  P.idx = plan->idx;
+  P.ldi = ldi;
+  P.scores = plan->scores;
+  P.frec = plan->frec;
+  P.flags = plan->dflags;
+  P.order = job->order;
+  P.edges = job->edges;
+  P.steps = job->steps;
+  P.step_gain = job->step_gain;
+  P.faces = job->faces;
+  P.status = job->status;
+  P.stats = plan->stats;
+  TMFG_HIP(tmfg::launch_loop(P, stream));
+  record(plan, 4, stream);
+  plan->timed = (plan->flags & TMFG_TIMING) != 0;
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]) {
+  if (!plan || !ms) return TMFG_E_INVALID;
+  if (!plan->timed) return TMFG_E_INVALID;
+  TMFG_HIP(hipEventSynchronize(plan->ev[4]));
+  for (int i = 0; i < 4; ++i) TMFG_HIP(hipEventElapsedTime(&ms[i], plan->ev[i], plan->ev[i + 1]));
+  TMFG_HIP(hipEventElapsedTime(&ms[4], plan->ev[0], plan->ev[4]));
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[4]) {
+  if (!plan || !out) return TMFG_E_INVALID;
+  TMFG_HIP(hipMemcpy(out, plan->stats, 16, hipMemcpyDeviceToHost));
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_correlation(tmfg_plan plan, const float* X, int32_t n, int32_t L, float* W, int32_t* status,
+                             hipStream_t stream) {
+  if (!plan || !X || !W || !status) return TMFG_E_INVALID;
+  if (!valid_n(n, plan->n_max) || L < 2 || L > plan->L_max) return TMFG_E_SIZE;
+  const Sizes s = sizes_for(n, L);
+  hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(1), 0, stream, plan->dflags);
+  TMFG_HIP(hipGetLastError());
+  TMFG_HIP(tmfg::launch_standardize(X, n, L, plan->Z, s.n_pad, s.L_pad, plan->dflags, stream));
+  TMFG_HIP(tmfg::launch_corr_gemm(plan->Z, n, s.L_pad, W, stream));
+  hipLaunchKernelGGL(flags_to_status_kernel, dim3(1), dim3(1), 0, stream, plan->dflags, status);
+  TMFG_HIP(hipGetLastError());
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, int64_t ld,
+                           hipStream_t stream) {
+  if (!plan || !W || !idx) return TMFG_E_INVALID;
+  if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
+  if (ld % 8 != 0 || ld < tmfg::sort_row_stride(n) || ((uintptr_t)idx & 15u)) return TMFG_E_INVALID;
+  TMFG_HIP(tmfg::launch_sort_rows(W, n, idx, ld, stream));
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_seed(tmfg_plan plan, const float* W, int32_t n, double* scores, int32_t* seed4,
+                      hipStream_t stream) {
+  if (!plan || !W || !scores || !seed4) return TMFG_E_INVALID;
+  if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
+  TMFG_HIP(tmfg::launch_seed_scores(W, n, scores, stream));
+  TMFG_HIP(tmfg::launch_seed_top4(scores, n, seed4, stream));
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_face_sweep(tmfg_plan plan, const float* W, int32_t n, const int32_t* faces, int32_t nfaces,
+                            const uint32_t* inserted, int32_t* best_u, float* best_gain, hipStream_t stream) {
+  if (!plan || !W || !faces || !inserted || !best_u || !best_gain) return TMFG_E_INVALID;
+  if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
+  if (nfaces < 0) return TMFG_E_SIZE;
+  TMFG_HIP(tmfg::launch_face_sweep(W, n, faces, nfaces, inserted, best_u, best_gain, stream));
+  return TMFG_OK;
+}
+
+}  // extern "C"

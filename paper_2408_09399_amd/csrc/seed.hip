@@ -1,0 +1,144 @@
+// Seed tetrahedron scores and the finite/symmetry validator.
+//
+// The four seed vertices are those with the largest total similarity across their row
+// (Algorithm 1 and Algorithm 2, first comment). This library reads that as: the sum over
+// u != v of W[v][u], accumulated in float64 strictly in index order of u, ranked by
+// (score desc, id asc).
+#include "common.h"
+#include "internal.h"
+
+namespace tmfg {
+
+// One thread per vertex v sums column v, which equals row v because W is bitwise
+// symmetric; adjacent threads read adjacent addresses, so each row of W is read once,
+// coalesced. Loads run a block ahead of the sequential float64 additions.
+__global__ __launch_bounds__(256) void seed_scores_kernel(const float* __restrict__ W, int n,
+                                                          double* __restrict__ scores) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v >= n) return;
+  constexpr int U = 32;
+  const float* col = W + v;
+  double acc = 0.0;
+  float cur[U], nxt[U];
+  int u = 0;
+  const int full = n / U * U;
+  if (full > 0) {
+#pragma unroll
+    for (int k = 0; k < U; ++k) cur[k] = col[(size_t)k * n];
+  }
+  for (; u < full; u += U) {
+    const bool more = u + U < full;
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) nxt[k] = col[(size_t)(u + U + k) * n];
+    }
+#pragma unroll
+    for (int k = 0; k < U; ++k) acc += (u + k == v) ? 0.0 : (double)cur[k];
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < U; ++k) cur[k] = nxt[k];
+    }
+  }
+  for (; u < n; ++u) acc += (u == v) ? 0.0 : (double)col[(size_t)u * n];
+  scores[v] = acc;
+}
+
+// Top-4 by (score desc, id asc), one 256-thread workgroup.
+__global__ __launch_bounds__(256) void seed_top4_kernel(const double* __restrict__ scores, int n,
+                                                        int32_t* __restrict__ seed4) {
+  __shared__ uint64_t sk[4];
+  __shared__ int sv[4];
+  __shared__ int chosen[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r = 0; r < 4; ++r) {
+    uint64_t bk = 0;
+    int bv = 0x7fffffff;
+    for (int v = tid; v < n; v += 256) {
+      bool skip = false;
+      for (int q = 0; q < r; ++q) skip |= (chosen[q] == v);
+      if (skip) continue;
+      const uint64_t k = ord_f64(scores[v]);
+      if (k > bk || (k == bk && v < bv)) {
+        bk = k;
+        bv = v;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t ok = ((uint64_t)__shfl_xor((uint32_t)(bk >> 32), off, kWave) << 32) |
+                          __shfl_xor((uint32_t)bk, off, kWave);
+      const int ov = __shfl_xor(bv, off, kWave);
+      if (ok > bk || (ok == bk && ov < bv)) {
+        bk = ok;
+        bv = ov;
+      }
+    }
+    if (lane == 0) {
+      sk[wave] = bk;
+      sv[wave] = bv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t k = sk[0];
+      int v = sv[0];
+      for (int w = 1; w < 4; ++w)
+        if (sk[w] > k || (sk[w] == k && sv[w] < v)) {
+          k = sk[w];
+          v = sv[w];
+        }
+      chosen[r] = v;
+      seed4[r] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Flags non-finite entries and entries whose mirror has different bits. Each 32x32 tile
+// (i0, j0) with i0 <= j0 is read directly and transposed through LDS.
+__global__ __launch_bounds__(256) void validate_kernel(const float* __restrict__ W, int n,
+                                                       uint32_t* __restrict__ flags) {
+  __shared__ uint32_t t[32][33];
+  const int nb = (n + 31) / 32;
+  int bi, bj;
+  upper_tri_coords(blockIdx.x, nb, bi, bj);
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  uint32_t bad = 0;
+  for (int r = ty; r < 32; r += 8) {
+    const int gi = bj * 32 + r, gj = bi * 32 + tx;   // the mirror tile, row-major
+    uint32_t bits = 0;
+    if (gi < n && gj < n) {
+      const float x = W[(size_t)gi * n + gj];
+      bits = __float_as_uint(x);
+      if (!isfinite(x)) bad |= kFlagNonFinite;
+    }
+    t[tx][r] = bits;
+  }
+  __syncthreads();
+  for (int r = ty; r < 32; r += 8) {
+    const int gi = bi * 32 + r, gj = bj * 32 + tx;
+    if (gi < n && gj < n) {
+      const float x = W[(size_t)gi * n + gj];
+      if (!isfinite(x)) bad |= kFlagNonFinite;
+      if (__float_as_uint(x) != t[r][tx]) bad |= kFlagAsymmetric;
+    }
+  }
+  if (bad) atomicOr(flags, bad);
+}
+
+hipError_t launch_seed_scores(const float* W, int n, double* scores, hipStream_t s) {
+  hipLaunchKernelGGL(seed_scores_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, n, scores);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_top4(const double* scores, int n, int32_t* seed4, hipStream_t s) {
+  hipLaunchKernelGGL(seed_top4_kernel, dim3(1), dim3(256), 0, s, scores, n, seed4);
+  return hipGetLastError();
+}
+
+hipError_t launch_validate(const float* W, int n, uint32_t* flags, hipStream_t s) {
+  const int nb = (n + 31) / 32;
+  hipLaunchKernelGGL(validate_kernel, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, W, n, flags);
+  return hipGetLastError();
+}
+
+}  // namespace tmfg

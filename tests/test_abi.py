@@ -1,0 +1,60 @@
+"""The C ABI library loads without a GPU, exports every declared symbol, and rejects bad
+arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2408_09399_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tmfg.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(tmfg_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_header_declares_what_binding_wraps():
+    assert declared_functions() == sorted(binding.SIGNATURES)
+
+
+def test_library_exports_every_symbol():
+    lib = binding.lib()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_status_strings():
+    lib = binding.lib()
+    for code in range(9):
+        assert lib.tmfg_status_string(code)
+
+
+def test_host_side_argument_errors():
+    lib = binding.lib()
+    h = ctypes.c_void_p()
+    assert lib.tmfg_plan_create(None, 100, 10, 0) == 1
+    assert lib.tmfg_plan_create(ctypes.byref(h), 3, 10, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 20481, 10, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 1, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1 << 9) == 1
+    assert lib.tmfg_build(None, None, None) == 1
+    assert lib.tmfg_correlation(None, None, 10, 10, None, None, None) == 1
+    assert lib.tmfg_sort_rows(None, None, 10, None, 16, None) == 1
+    assert lib.tmfg_seed(None, None, 10, None, None, None) == 1
+    assert lib.tmfg_face_sweep(None, None, 10, None, 1, None, None, None, None) == 1
+    assert lib.tmfg_plan_destroy(None) == 0
+    assert lib.tmfg_plan_phase_ms(None, None) == 1
+    assert lib.tmfg_plan_stats(None, None) == 1
+
+
+def test_footprint_grows_quadratically():
+    f1 = binding.footprint_bytes(5000, 512)
+    f2 = binding.footprint_bytes(10000, 512)
+    assert 3.5 < f2 / f1 < 4.5
+    assert binding.footprint_bytes(3, 10) == 0

@@ -1,0 +1,26 @@
+"""The largest single-build workload (n=20000 series, L=1024) end to end: the full TMFG
+bit-exact against the lazy exact oracle fed the GPU's W bytes, plus invariants."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_09399_amd as tm
+from paper_2408_09399_amd import synth
+from gpu_util import to_dev, same_tmfg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.timeout(900)
+def test_c3_full_parity():
+    s = synth.config_c3()
+    res = tm.build(X=to_dev(s.X), keep_w=True)
+    torch.cuda.synchronize()
+    got = res.to_numpy()
+    assert got["status"] == 0
+    W = got["W"]
+    print("c3: GPU build done, running the oracle", flush=True)
+    ref = oracle.tmfg_lazy(W)
+    same_tmfg(got, ref)
+    oracle.check_tmfg(W, got, planarity=False)

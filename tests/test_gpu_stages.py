@@ -1,0 +1,99 @@
+"""Row sort, seed scores and the bulk face sweep on the GPU vs the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_09399_amd as tm
+from paper_2408_09399_amd import synth
+from gpu_util import to_dev, uint16_rows
+
+pytestmark = pytest.mark.gpu
+
+
+def _sort_check(W: np.ndarray, rows=None):
+    n = W.shape[0]
+    idx = tm.sort_rows(to_dev(W))
+    torch.cuda.synchronize()
+    got = uint16_rows(idx, n)
+    rows = range(n) if rows is None else rows
+    for v in rows:
+        ref = oracle.sorted_row(W, v)
+        if not np.array_equal(got[v], ref):
+            bad = np.flatnonzero(got[v] != ref)[:5]
+            raise AssertionError(f"row {v} differs at {bad.tolist()}")
+
+
+@pytest.mark.parametrize("n", [4, 5, 63, 64, 65, 200, 257, 1000, 1025, 2049, 4097])
+def test_sort_random(n):
+    _sort_check(synth.random_symmetric(n, n))
+
+
+@pytest.mark.parametrize("n,levels", [(50, 2), (300, 4), (1500, 8), (700, 1)])
+def test_sort_tie_heavy(n, levels):
+    W = synth.grid_symmetric(n, n + levels, levels=levels)
+    W[0, 1] = W[1, 0] = np.float32(-0.0)
+    W[0, 2] = W[2, 0] = np.float32(0.0)
+    _sort_check(W)
+
+
+def test_sort_all_equal():
+    W = np.full((900, 900), 0.25, dtype=np.float32)
+    np.fill_diagonal(W, 1.0)
+    _sort_check(W, rows=[0, 1, 450, 899])
+
+
+def test_sort_pearson_c2_sampled():
+    s = synth.config_c2()
+    W, _ = tm.correlation(to_dev(s.X))
+    _sort_check(W.cpu().numpy(), rows=list(range(0, 5000, 97)) + [4999])
+
+
+def test_sort_max_n():
+    n = 20480
+    rng = np.random.default_rng(5)
+    rows = rng.choice(n, 6, replace=False)
+    W = synth.random_symmetric(n, 77)
+    _sort_check(W, rows=list(rows))
+
+
+@pytest.mark.parametrize("n", [4, 7, 200, 1031, 5000])
+def test_seed(n):
+    W = synth.random_symmetric(n, 1000 + n)
+    scores, s4 = tm.seed(to_dev(W))
+    torch.cuda.synchronize()
+    ref = oracle.seed_scores(W)
+    assert np.array_equal(scores.cpu().numpy(), ref)
+    assert s4.cpu().tolist() == oracle.seed_vertices(W)
+
+
+def test_seed_ties():
+    W = synth.grid_symmetric(300, 9, levels=2)
+    scores, s4 = tm.seed(to_dev(W))
+    torch.cuda.synchronize()
+    assert np.array_equal(scores.cpu().numpy(), oracle.seed_scores(W))
+    assert s4.cpu().tolist() == oracle.seed_vertices(W)
+
+
+@pytest.mark.parametrize("n,levels", [(300, 0), (1200, 0), (400, 4)])
+def test_face_sweep(n, levels):
+    rng = np.random.default_rng(n)
+    W = synth.random_symmetric(n, n) if levels == 0 else synth.grid_symmetric(n, n, levels=levels)
+    F = 500
+    faces = np.stack([rng.choice(n, 3, replace=False) for _ in range(F)]).astype(np.int32)
+    if levels == 0:
+        ins = rng.random(n) < 0.6
+    else:                                    # nearly everything inserted
+        ins = np.ones(n, dtype=bool)
+        ins[rng.choice(n, 3, replace=False)] = False
+    ins[faces.ravel()] = True
+    words = np.zeros((n + 31) // 32, dtype=np.uint32)
+    for u in np.flatnonzero(ins):
+        words[u >> 5] |= np.uint32(1 << (u & 31))
+    bu, bg = tm.face_sweep(to_dev(W), to_dev(faces), to_dev(words.view(np.int32)))
+    torch.cuda.synchronize()
+    bu, bg = bu.cpu().numpy(), bg.cpu().numpy()
+    for f in range(F):
+        u, g = oracle.face_best(W, sorted(faces[f].tolist()), ins)
+        assert bu[f] == u, f
+        assert np.float32(bg[f]).tobytes() == np.float32(g).tobytes(), f
