@@ -44,7 +44,7 @@ def check_tmfg(W: np.ndarray, res: Dict[str, np.ndarray], planarity: bool = True
         assert 0 <= f < len(live) and live[f] == (x, y, z), "step joins a live face"
         assert x < y < z
         assert edges[6 + 3 * i: 9 + 3 * i] == [(u, x), (u, y), (u, z)]
-        g = (W[x, u] + W[y, u]) + W[z, u]
+        g = (W[x, u] + W[y, u]) + W[z, u] + np.float32(0.0)    # -0.0 is recorded as +0.0
         assert np.float32(g).tobytes() == gains[i].tobytes(), "recorded gain matches W"
         live[f] = tuple(sorted((u, x, y)))
         live.append(tuple(sorted((u, y, z))))

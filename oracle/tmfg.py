@@ -26,6 +26,8 @@ Readings where the paper is silent (each applies to every function in this modul
      (v1,v2),(v1,v3),(v1,v4),(v2,v3),(v2,v4),(v3,v4), then (u,x),(u,y),(u,z) per step),
      steps (f, x, y, z) per step, step_gain per step, faces (final corner triples in
      face-id order).
+  R8 signed zero: -0.0 and +0.0 compare equal everywhere (selection, ties), and a gain of
+     zero is recorded as +0.0.
 
 Three schedules compute the same result (the cached one and the heap one rest on the
 fact that removing vertices from the candidate set never raises a face's best gain):
@@ -125,6 +127,11 @@ def _split(faces: List[tuple], f: int, u: int):
     return x, y, z
 
 
+def _rec_gain(g) -> np.float32:
+    """R8: the recorded gain, with -0.0 written as +0.0 (adding +0.0 does exactly that)."""
+    return np.float32(g) + np.float32(0.0)
+
+
 def _result(order, edges, steps, gains, faces) -> Dict[str, np.ndarray]:
     return {
         "order": np.asarray(order, dtype=np.int32),
@@ -161,7 +168,7 @@ def tmfg_exact(W: np.ndarray) -> Dict[str, np.ndarray]:
         x, y, z = _split(faces, fstar, u)
         edges += [(u, x), (u, y), (u, z)]
         steps.append((fstar, x, y, z))
-        gains.append(g)
+        gains.append(_rec_gain(g))
         live += 2
         if inserted.all():
             break
@@ -198,7 +205,7 @@ def tmfg_lazy(W: np.ndarray) -> Dict[str, np.ndarray]:
         x, y, z = _split(faces, f, u)
         edges += [(u, x), (u, y), (u, z)]
         steps.append((f, x, y, z))
-        gains.append(np.float32(-neg_g))
+        gains.append(_rec_gain(-neg_g))
         if len(order) < n:
             for nf in (f, len(faces) - 2, len(faces) - 1):
                 u2, g2 = face_best(W, faces[nf], inserted)
@@ -246,5 +253,5 @@ def tmfg_bruteforce(W: np.ndarray) -> Dict[str, np.ndarray]:
         x, y, z = _split(faces, f, u)
         edges += [(u, x), (u, y), (u, z)]
         steps.append((f, x, y, z))
-        gains.append(G[f, j])
+        gains.append(_rec_gain(G[f, j]))
     return _result(order, edges, steps, gains, faces)

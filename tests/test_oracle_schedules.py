@@ -89,3 +89,15 @@ def test_wrong_addition_order_would_fail_golden():
     right = (W[a, 5] + W[b, 5]) + W[c, 5]
     wrong = W[a, 5] + (W[b, 5] + W[c, 5])
     assert right == np.float32(1.0) and wrong > np.float32(1.0)
+
+
+def test_signed_zero_gain_recorded_positive():
+    # A face whose best gain is exactly zero from -0.0 entries: -0 == +0 in every
+    # comparison, and the recorded gain is +0.0.
+    W = np.full((5, 5), 0.5, dtype=np.float32)
+    np.fill_diagonal(W, 1.0)
+    W[4, :4] = W[:4, 4] = np.float32(-0.0)
+    for fn in (oracle.tmfg_exact, oracle.tmfg_lazy, oracle.tmfg_bruteforce):
+        r = fn(W)
+        assert r["step_gain"].view(np.uint32).tolist() == [0]
+        oracle.check_tmfg(W, r)
