@@ -152,8 +152,10 @@ def main():
         "corr_gemm": ("mfma", gemm_tflops, PEAK_FP32_MFMA_TFLOPS, "TFLOP/s", ph[0]),
         "sort_rows": ("hbm", sort_gbs, PEAK_HBM_GBS, "GB/s", ph[2]),
     }
-    walk_rounds = stats[1]
-    loop_bytes = walk_rounds * (3 * 64 * 2 + 3 * 64 * 3 * 4 + 3 * 4)
+    # per walk round: 64 list entries (2-byte id + 4-byte value) from each of the three
+    # lists; plus every similarity a walk had to read from W
+    walk_rounds, gathers = stats[1], stats[11]
+    loop_bytes = walk_rounds * 3 * 64 * 6 + gathers * 4
     loop_gbs = loop_bytes / (ph[3] * 1e-3) / 1e9
     kernels["tmfg_loop"] = ("hbm", loop_gbs, PEAK_HBM_GBS, "GB/s", ph[3])
     dom = max(kernels, key=lambda k: kernels[k][4])
@@ -178,7 +180,11 @@ def main():
         "corr_gemm_tflops": round(gemm_tflops, 2),
         "row_sort_gbs": round(sort_gbs, 1),
         "loop_stats": {"stale_recomputes": stats[0], "walk_rounds": stats[1], "sweeps": stats[2],
-                       "phases": stats[3]},
+                       "phases": stats[3], "walk_batches": stats[4], "w_reads": stats[11],
+                       "critical_rounds": stats[12], "walks_ge4": stats[13], "walks_ge16": stats[14],
+                       "skip_scans": stats[15],
+                       "us": {"select": stats[5], "load": stats[6], "walk": stats[7],
+                              "sweep": stats[8], "publish": stats[9], "kernel": stats[10]}},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -107,9 +107,16 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream);
    last event. */
 tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
 
-/* Counters of the plan's last build (synchronous copy): [0] stale face recomputes,
-   [1] walk rounds, [2] full-row sweeps, [3] selection phases. */
-tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[4]);
+/* Counters of the plan's last build (synchronous copy of 16 int32): [0] stale face
+   recomputes, [1] walk rounds, [2] full-row sweeps, [3] selection phases, [4] walk
+   batches, [5..9] microseconds spent in selection, chunk loading, walks, sweeps and
+   publishing, [10] microseconds of the whole loop kernel, [11] similarities read from W
+   by walks (those not carried by the sorted rows), [12] sum over selection phases of the
+   deepest walk's rounds, [13] walks of 4 or more rounds, [14] walks of 16 or more rounds,
+   [15] skip scans over fully inserted stretches, [16..19] microseconds one walk group
+   spent loading and ranking list entries, reading candidate similarities, updating
+   bounds, and skip-scanning (diagnostics), [20..31] reserved. */
+tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
 
 /* ---- The stages of a build, callable on their own ------------------------------- */
 
@@ -121,11 +128,13 @@ tmfg_status tmfg_correlation(tmfg_plan plan, const float* X, int32_t n, int32_t 
                              int32_t* status, hipStream_t stream);
 
 /* Per-vertex order (Algorithm 1, sort of each row of S): idx[v*ld + k], k < n-1, is the
-   k-th vertex u != v by (W[v][u] desc, u asc), as uint16. ld must be a multiple of 8 and
-   at least n-1 rounded up to 8; idx must be 16-byte aligned; entries n-1..ld-1 of each
-   row are overwritten with 0xffff up to the next multiple of 8. */
-tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, int64_t ld,
-                           hipStream_t stream);
+   k-th vertex u != v by (W[v][u] desc, u asc), as uint16; if vals is not NULL,
+   vals[v*ld + k] = W[v][idx[v*ld + k]] as float32 (-0.0 written as +0.0). ld must be a
+   multiple of 8 and at least n-1 rounded up to 8; idx and vals must be 16-byte aligned;
+   entries n-1 up to the next multiple of 8 of each row are overwritten (idx 0xffff,
+   vals -inf). */
+tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, float* vals,
+                           int64_t ld, hipStream_t stream);
 
 /* Seed (Algorithms 1 and 2, first comment): scores[v] = float64 sum of W[v][u] over
    u != v in index order; seed4 = the four largest by (score desc, id asc). W must be

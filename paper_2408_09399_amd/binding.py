@@ -34,7 +34,7 @@ SIGNATURES = {
     "tmfg_plan_phase_ms": (_I, [_P, ctypes.POINTER(ctypes.c_float)]),
     "tmfg_plan_stats": (_I, [_P, ctypes.POINTER(_I)]),
     "tmfg_correlation": (_I, [_P, _P, _I, _I, _P, _P, _P]),
-    "tmfg_sort_rows": (_I, [_P, _P, _I, _P, ctypes.c_int64, _P]),
+    "tmfg_sort_rows": (_I, [_P, _P, _I, _P, _P, ctypes.c_int64, _P]),
     "tmfg_seed": (_I, [_P, _P, _I, _P, _P, _P]),
     "tmfg_face_sweep": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P]),
     "tmfg_status_string": (ctypes.c_char_p, [_I]),
@@ -152,7 +152,7 @@ class Plan:
         return tuple(float(x) for x in out)
 
     def stats(self) -> Tuple[int, ...]:
-        out = (ctypes.c_int32 * 4)()
+        out = (ctypes.c_int32 * 32)()
         _check(_lib().tmfg_plan_stats(self.handle, out), "tmfg_plan_stats")
         return tuple(int(x) for x in out)
 
@@ -237,8 +237,9 @@ def sort_stride(n: int) -> int:
     return (max(n - 1, 1) + 7) // 8 * 8
 
 
-def sort_rows(W, plan: Optional[Plan] = None, stream=None):
-    """Per-vertex order as an (n, ld) int16 tensor holding uint16 ids (first n-1 valid)."""
+def sort_rows(W, plan: Optional[Plan] = None, stream=None, with_values: bool = False):
+    """Per-vertex order as an (n, ld) int16 tensor holding uint16 ids (first n-1 valid),
+    plus the (n, ld) float32 similarities in that order when with_values is set."""
     import torch
     W = _need(W, torch.float32, "W")
     n = W.shape[0]
@@ -246,8 +247,10 @@ def sort_rows(W, plan: Optional[Plan] = None, stream=None):
         plan = Plan(n, 2)
     ld = sort_stride(n)
     idx = torch.empty((n, ld), dtype=torch.int16, device=W.device)
-    _check(_lib().tmfg_sort_rows(plan.handle, _ptr(W), n, _ptr(idx), ld, _stream(stream)), "tmfg_sort_rows")
-    return idx
+    vals = torch.empty((n, ld), dtype=torch.float32, device=W.device) if with_values else None
+    _check(_lib().tmfg_sort_rows(plan.handle, _ptr(W), n, _ptr(idx), _ptr(vals), ld, _stream(stream)),
+           "tmfg_sort_rows")
+    return (idx, vals) if with_values else idx
 
 
 def seed(W, plan: Optional[Plan] = None, stream=None):

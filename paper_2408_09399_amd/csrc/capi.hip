@@ -36,7 +36,7 @@ struct Sizes {
   int n, L;
   int n_pad, L_pad;
   int64_t ldi;
-  size_t z_bytes, w_bytes, idx_bytes, scores_bytes, frec_bytes;
+  size_t z_bytes, w_bytes, idx_bytes, vals_bytes, scores_bytes, frec_bytes;
 };
 
 Sizes sizes_for(int n, int L) {
@@ -49,6 +49,7 @@ Sizes sizes_for(int n, int L) {
   s.z_bytes = (size_t)s.n_pad * s.L_pad * sizeof(float);
   s.w_bytes = (size_t)n * n * sizeof(float);
   s.idx_bytes = (size_t)n * s.ldi * sizeof(uint16_t);
+  s.vals_bytes = (size_t)n * s.ldi * sizeof(float);
   s.scores_bytes = (size_t)n * sizeof(double);
   s.frec_bytes = (size_t)(2 * n - 4) * 16;
   return s;
@@ -64,12 +65,14 @@ struct tmfg_plan_s {
   float* Z = nullptr;
   float* W = nullptr;
   uint16_t* idx = nullptr;
+  float* vals = nullptr;
   double* scores = nullptr;
   uint4* frec = nullptr;
   uint32_t* dflags = nullptr;
   int32_t* stats = nullptr;
   hipEvent_t ev[kPhaseEvents] = {};
   bool timed = false;
+  int wall_khz = 100000;   // device wall-clock counter rate
 };
 
 namespace {
@@ -79,6 +82,7 @@ void plan_free(tmfg_plan p) {
   hipFree(p->Z);
   hipFree(p->W);
   hipFree(p->idx);
+  hipFree(p->vals);
   hipFree(p->scores);
   hipFree(p->frec);
   hipFree(p->dflags);
@@ -129,7 +133,7 @@ size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags) {
   (void)flags;
   if (n_max < tmfg::kMinN) return 0;
   const Sizes s = sizes_for(n_max, L_max);
-  return s.z_bytes + s.w_bytes + s.idx_bytes + s.scores_bytes + s.frec_bytes + 256 * 2;
+  return s.z_bytes + s.w_bytes + s.idx_bytes + s.vals_bytes + s.scores_bytes + s.frec_bytes + 256 * 2;
 }
 
 tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags) {
@@ -144,6 +148,9 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint
     delete p;
     return hip_fail(e);
   }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, p->device) == hipSuccess && khz > 0)
+    p->wall_khz = khz;
   p->n_max = n_max;
   p->L_max = L_max;
   p->flags = flags;
@@ -152,9 +159,10 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint
   if ((st = alloc((void**)&p->Z, p->sz.z_bytes)) != TMFG_OK ||
       (st = alloc((void**)&p->W, p->sz.w_bytes)) != TMFG_OK ||
       (st = alloc((void**)&p->idx, p->sz.idx_bytes)) != TMFG_OK ||
+      (st = alloc((void**)&p->vals, p->sz.vals_bytes)) != TMFG_OK ||
       (st = alloc((void**)&p->scores, p->sz.scores_bytes)) != TMFG_OK ||
       (st = alloc((void**)&p->frec, p->sz.frec_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->dflags, 4)) != TMFG_OK || (st = alloc((void**)&p->stats, 16)) != TMFG_OK) {
+      (st = alloc((void**)&p->dflags, 4)) != TMFG_OK || (st = alloc((void**)&p->stats, 128)) != TMFG_OK) {
     plan_free(p);
     return st;
   }
@@ -206,12 +214,13 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
   TMFG_HIP(tmfg::launch_seed_scores(Wt, n, plan->scores, stream));
   record(plan, 2, stream);
   const int64_t ldi = tmfg::sort_row_stride(n);
-  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, plan->idx, ldi, stream));
+  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, plan->idx, plan->vals, ldi, stream));
   record(plan, 3, stream);
   tmfg::LoopParams P{};
   P.W = Wt;
   P.n = n;
   P.idx = plan->idx;
+  P.vals = plan->vals;
   P.ldi = ldi;
   P.scores = plan->scores;
   P.frec = plan->frec;
@@ -238,9 +247,11 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]) {
   return TMFG_OK;
 }
 
-tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[4]) {
+tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]) {
   if (!plan || !out) return TMFG_E_INVALID;
-  TMFG_HIP(hipMemcpy(out, plan->stats, 16, hipMemcpyDeviceToHost));
+  TMFG_HIP(hipMemcpy(out, plan->stats, 128, hipMemcpyDeviceToHost));
+  for (int i = 5; i <= 10; ++i) out[i] = (int32_t)((int64_t)out[i] * 1000 / plan->wall_khz);
+  for (int i = 16; i < 20; ++i) out[i] = (int32_t)((int64_t)out[i] * 1000 / plan->wall_khz);
   return TMFG_OK;
 }
 
@@ -258,12 +269,13 @@ tmfg_status tmfg_correlation(tmfg_plan plan, const float* X, int32_t n, int32_t 
   return TMFG_OK;
 }
 
-tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, int64_t ld,
+tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, float* vals, int64_t ld,
                            hipStream_t stream) {
   if (!plan || !W || !idx) return TMFG_E_INVALID;
   if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
-  if (ld % 8 != 0 || ld < tmfg::sort_row_stride(n) || ((uintptr_t)idx & 15u)) return TMFG_E_INVALID;
-  TMFG_HIP(tmfg::launch_sort_rows(W, n, idx, ld, stream));
+  if (ld % 8 != 0 || ld < tmfg::sort_row_stride(n) || ((uintptr_t)idx & 15u) || ((uintptr_t)vals & 15u))
+    return TMFG_E_INVALID;
+  TMFG_HIP(tmfg::launch_sort_rows(W, n, idx, vals, ld, stream));
   return TMFG_OK;
 }
 

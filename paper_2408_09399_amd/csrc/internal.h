@@ -20,8 +20,9 @@ hipError_t launch_seed_scores(const float* W, int n, double* scores, hipStream_t
 // Top-4 of the scores (score desc, id asc) in rank order (one small workgroup).
 hipError_t launch_seed_top4(const double* scores, int n, int32_t* seed4, hipStream_t s);
 
-// Per-row order of the other vertices: (W[v][u] desc, u asc); u16 ids, row stride ldi.
-hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, int64_t ldi, hipStream_t s);
+// Per-row order of the other vertices: (W[v][u] desc, u asc); u16 ids, and optionally the
+// float32 similarities in the same order, both with row stride ldi.
+hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s);
 int64_t sort_row_stride(int n);
 
 // Exact best vertex of many faces by a full sweep of their three rows.
@@ -32,6 +33,7 @@ struct LoopParams {
   const float* W;
   int n;
   const uint16_t* idx;
+  const float* vals;       // similarities in idx order (same row stride)
   int64_t ldi;
   const double* scores;
   uint4* frec;             // 2n-4 face records (scratch)
@@ -42,7 +44,7 @@ struct LoopParams {
   float* step_gain;
   int32_t* faces;
   int32_t* status;
-  int32_t* stats;          // optional: [0] stale recomputes, [1] walk rounds, [2] sweeps, [3] phases
+  int32_t* stats;          // optional, 16 counters (see tmfg_plan_stats)
 };
 hipError_t launch_loop(const LoopParams& p, hipStream_t s);
 size_t loop_lds_bytes(int n);

@@ -10,30 +10,57 @@
 // Each face keeps a cached best pair. Removing vertices never raises a face's best gain,
 // so a cached pair whose vertex is still uninserted is exact and one whose vertex has been
 // inserted ("stale") is an upper bound. As in the paper's heap-based variant (Section 4.2)
-// stale pairs are recomputed lazily, only when they could decide the next insertion. The
-// global maximum is tracked with a two-level structure instead of a heap: face records in
-// global memory (16 B each), and per 64-face chunk the maximum record in LDS; wave 0 scans
-// the chunk maxima. If the top record is fresh it is inserted; otherwise every stale chunk
-// maximum ranked above the best fresh one (up to one per wave) is recomputed in parallel.
+// stale pairs are recomputed lazily, only when they could decide an insertion. The global
+// maximum is tracked with a two-level structure instead of a heap: face records in global
+// memory (16 B each) and, per 64-face chunk, the maximum record in LDS.
 //
-// Best vertex of a face (one wave): the threshold walk over the three corners' sorted rows
-// (the per-vertex sort of Algorithm 1). Each round reads the next 64 entries of each list,
-// skipping inserted vertices (the first uninserted position per vertex is cached in LDS:
-// the paper's MaxCorrs), and evaluates every uninserted candidate exactly. Any vertex not
-// yet seen has W[x][u] <= the value at the last position read from x's list, for x = a, b,
-// c, so its gain is at most T = (A + B) + C of those three values (float32 addition is
-// monotone). The walk stops when the best gain seen is strictly above T, or a list is
-// exhausted. A walk that needs more than kMaxRounds rounds is finished by a sweep of the
-// three full rows by the whole workgroup. Both give the exact best pair.
+// One selection phase (wave 0 scans the chunk maxima):
+//   * if the top record is fresh, its vertex is inserted; the chunks of the three new
+//     faces are queued, plus every chunk whose maximum is stale once that vertex is
+//     inserted and ranks above the best fresh record that remains;
+//   * otherwise every chunk whose maximum is stale and ranks above the best fresh record
+//     is queued.
+// Every queued chunk is loaded (one wave each). Its stale records ranked above that floor
+// and the new faces are recomputed in parallel (one group of 16 lanes per face), published,
+// and the chunk maxima are rebuilt from the loaded records.
+//
+// Best vertex of a face: the threshold walk over the three corners' sorted rows (the
+// per-vertex sort of Algorithm 1, with the similarity of every entry stored beside its id).
+// Each round takes the first kCand uninserted entries at or after each list's position and
+// evaluates them; a vertex found in several of the three lists is evaluated once, with the
+// similarities those lists carry, and only the missing ones are read from W. Any vertex
+// not yet evaluated has W[x][u] <= the value of the bound entry of x's list (the next
+// uninserted entry, or the last position scanned) for x = a, b, c, so its gain is at most
+// T = (A + B) + C of those values (float32 addition is monotone). The walk stops when the
+// best gain seen is strictly above T, or a list is used up. Every walk moves each list's
+// cached start (the first uninserted position: the paper's MaxCorrs pointer) forward. A
+// walk that needs more than kMaxRounds rounds is finished by a sweep of the three full
+// rows by the whole workgroup. Both give the exact best pair.
 #include "common.h"
 #include "internal.h"
 
 namespace tmfg {
 
 namespace {
-constexpr int kBlock = 1024;
+constexpr int kBlock = 512;
 constexpr int kWaves = kBlock / kWave;
-constexpr int kMaxRounds = 8;
+constexpr int kGroup = 16;                       // lanes per face walk
+constexpr int kGroups = kBlock / kGroup;         // face walks in flight
+constexpr int kScan = 4;                         // list entries per lane and round
+constexpr int kSpan = kScan * kGroup;            // list positions scanned per round
+constexpr int kCand = 8;                         // candidates taken per list and round
+constexpr int kSkipLoads = 4;                    // 16-byte loads per lane in a skip scan
+constexpr int kMaxRounds = 64;
+constexpr int kMaxWork = 128;                    // faces recomputed per selection phase
+constexpr int kMaxSel = 16;                      // chunks loaded per selection phase
+// Time the sub-steps of one walk group (stats [16..19]); the waits it adds slow that group.
+constexpr bool kWalkDiag = false;
+
+// Per-group staging of a walk round's candidates.
+struct GroupBuf {
+  uint16_t cid[3 * kCand];
+  float cval[3 * kCand];
+};
 
 struct Work {
   int f;            // face id
@@ -41,6 +68,7 @@ struct Work {
   uint64_t best;    // (ord(gain) << 32) | (0xffff - u), 0 when no candidate
   int sweep;        // 1 when the walk gave up and a full sweep is needed
 };
+
 
 __device__ __forceinline__ bool is_ins(const uint32_t* bits, int u) { return (bits[u >> 5] >> (u & 31)) & 1u; }
 
@@ -55,82 +83,269 @@ __device__ __forceinline__ void sort3(int& x, int& y, int& z) {
   if (x > y) { t = x; x = y; y = t; }
 }
 
-// Threshold walk for one face by one wave. Returns false when it ran out of rounds.
-__device__ bool walk_face(const LoopParams& P, const uint32_t* bits, uint16_t* ptr, int a, int b, int c,
-                          uint64_t& best_out, int lane, int* rounds) {
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+#pragma unroll
+  for (int off = kGroup / 2; off >= 1; off >>= 1) {
+    uint32_t lo = __shfl_xor((uint32_t)v, off, kWave);
+    uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, kWave);
+    uint64_t o = ((uint64_t)hi << 32) | lo;
+    v = o > v ? o : v;
+  }
+  return v;
+}
+__device__ __forceinline__ int group_incl_scan(int x, int gl) {
+#pragma unroll
+  for (int off = 1; off < kGroup; off <<= 1) {
+    const int y = __shfl_up(x, off, kGroup);
+    if (gl >= off) x += y;
+  }
+  return x;
+}
+__device__ __forceinline__ int group_min_i32(int x) {
+#pragma unroll
+  for (int off = kGroup / 2; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off, kWave));
+  return x;
+}
+
+// Threshold walk for one face by a group of kGroup lanes (gl = lane within the group,
+// gbase = first lane of the group).
+//
+// Each round scans kSpan positions of every list (kScan per lane) and takes the first kCand
+// uninserted entries at or after the list's position; the lane that holds such an entry
+// evaluates it, with the similarity to that list's corner carried by the sorted row and the
+// other two read from W. Ranks come from four ballots over the group (positions are ordered
+// by lane, then by entry). An uninserted vertex not yet evaluated sits after the list's
+// bound entry (the next uninserted entry, or the last position scanned), so its similarity
+// to that corner is at most the bound entry's value. A list whose span holds no uninserted
+// entry is then scanned kSkipLoads * 128 positions at a time (bitmap only) until one is
+// found. The code is written without data-dependent branches around loads, so each round
+// costs two dependent trips to memory (list entries, then candidate similarities), plus one
+// per skip scan. Returns false when it ran out of rounds.
+__device__ bool walk_face(const LoopParams& P, const uint32_t* bits, uint16_t* ptr, GroupBuf& gb, int a, int b,
+                          int c, int gl, int gbase, uint64_t& best_out, int* rounds, int* gathers, int* skips,
+                          unsigned long long* wt) {
   const int n = P.n, m = n - 1;
-  const float* Wa = P.W + (size_t)a * n;
-  const float* Wb = P.W + (size_t)b * n;
-  const float* Wc = P.W + (size_t)c * n;
+  const int ldi = (int)P.ldi;
   const int x3[3] = {a, b, c};
-  int p[3];
-  bool skip[3];
-  int np[3];
+  const float* Wx[3] = {P.W + (size_t)a * n, P.W + (size_t)b * n, P.W + (size_t)c * n};
+  const uint64_t gmask = ((1ull << kGroup) - 1) << gbase;
+  const uint64_t below = ((1ull << gl) - 1) << gbase;     // lanes of my group before me
+  int pos[3], newp[3];
+  bool tight[3], skip[3];
 #pragma unroll
   for (int t = 0; t < 3; ++t) {
-    p[t] = ptr[x3[t]];
-    skip[t] = true;
-    np[t] = p[t];
+    pos[t] = ptr[x3[t]];              // every entry before it is inserted
+    newp[t] = pos[t];
+    tight[t] = false;
+    skip[t] = false;
   }
   uint64_t best = 0;
   bool done = false;
-  int r = 0;
+  int r = 0, ng = 0;
+#define TMFG_WT(i)                                                  \
+  if (wt) {                                                         \
+    asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)" ::: "memory");     \
+    const uint64_t c_ = wall_clock64();                             \
+    if (gl == 0) wt[i] += c_ - tw;                                  \
+    tw = c_;                                                        \
+  }
+  uint64_t tw = wt ? wall_clock64() : 0;
   for (; r < kMaxRounds && !done; ++r) {
-    int id[3];
-    bool ok[3];
+    // (1) this round's span of every list: ids and similarities (addresses kept inside
+    //     the row; entries at or past m are masked below)
+    int q[3];
+    uint2 iv[3];
+    float4 vv[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      const int pos = p[t] + r * kWave + lane;
-      id[t] = pos < m ? (int)P.idx[(size_t)x3[t] * P.ldi + pos] : -1;
-      ok[t] = id[t] >= 0 && !is_ins(bits, id[t]);
+      q[t] = (pos[t] & ~(kScan - 1)) + kScan * gl;
+      const int qc = min(q[t], ldi - kScan);
+      const size_t off = (size_t)x3[t] * ldi + qc;
+      iv[t] = *(const uint2*)(P.idx + off);
+      vv[t] = *(const float4*)(P.vals + off);
     }
-    // gains of uninserted candidates, plus the value at the last position of each list
-    float g[3], last[3];
+    // (2) uninserted entries, their ranks, and which are taken this round
+    int id[3][kScan];
+    float val[3][kScan];
+    uint32_t um[3], take[3];
+    int seen[3], bl[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      g[t] = 0.0f;
-      if (ok[t]) {
-        const int u = id[t];
-        g[t] = (Wa[u] + Wb[u]) + Wc[u];
+      const uint32_t wd[2] = {iv[t].x, iv[t].y};
+      val[t][0] = vv[t].x;
+      val[t][1] = vv[t].y;
+      val[t][2] = vv[t].z;
+      val[t][3] = vv[t].w;
+      um[t] = 0;
+#pragma unroll
+      for (int j = 0; j < kScan; ++j) {
+        id[t][j] = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const int p = q[t] + j;
+        const bool ok = !skip[t] && p >= pos[t] && p < m && !is_ins(bits, id[t][j] < n ? id[t][j] : 0);
+        um[t] |= ok ? (1u << j) : 0u;
       }
-      const int u63 = __shfl(id[t], 63, kWave);
-      last[t] = u63 >= 0 ? P.W[(size_t)x3[t] * n + u63] : -INFINITY;
+      int before = 0;
+      seen[t] = 0;
+#pragma unroll
+      for (int j = 0; j < kScan; ++j) {
+        const uint64_t bj = __ballot((um[t] >> j) & 1u) & gmask;
+        before += __popcll(bj & below);
+        seen[t] += __popcll(bj);
+      }
+      // the first kCand go to slots t*kCand + rank of the group's buffer; the entry of rank
+      // kCand (if any) is the list's bound entry
+      bl[t] = -1;
+#pragma unroll
+      for (int j = 0; j < kScan; ++j) {
+        const int rank = before + __popc(um[t] & ((1u << j) - 1));
+        const bool on = (um[t] >> j) & 1u;
+        if (on && rank < kCand) {
+          gb.cid[t * kCand + rank] = (uint16_t)id[t][j];
+          gb.cval[t * kCand + rank] = val[t][j];
+        }
+        bl[t] = (on && rank == kCand) ? j : bl[t];
+      }
+      take[t] = seen[t] < kCand ? seen[t] : kCand;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    TMFG_WT(0);
+    // (3) evaluate the staged candidates, two slots per lane; the two similarities not
+    //     carried by the list are read from W, all loads issued before any is used
+    int su[2], st[2];
+    float sv[2], sw[2][2];
+    bool sok[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int sl = gl + e * kGroup;
+      const int t = sl / kCand;
+      st[e] = t;
+      sok[e] = sl < 3 * kCand && (sl - t * kCand) < (int)(t == 0 ? take[0] : t == 1 ? take[1] : take[2]);
+      su[e] = sok[e] ? (int)gb.cid[sl] : 0;
+      sv[e] = sok[e] ? gb.cval[sl] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int t = st[e];
+      const float* o1 = t == 0 ? Wx[1] : Wx[0];
+      const float* o2 = t == 2 ? Wx[1] : Wx[2];
+      sw[e][0] = o1[su[e]];
+      sw[e][1] = o2[su[e]];
     }
     uint64_t k = 0;
 #pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const int t = st[e];
+      float w0, w1, w2;
+      if (t == 0) { w0 = sv[e]; w1 = sw[e][0]; w2 = sw[e][1]; }
+      else if (t == 1) { w0 = sw[e][0]; w1 = sv[e]; w2 = sw[e][1]; }
+      else { w0 = sw[e][0]; w1 = sw[e][1]; w2 = sv[e]; }
+      const uint64_t kt = cand_key((w0 + w1) + w2, su[e]);
+      k = (sok[e] && kt > k) ? kt : k;
+      ng += sok[e] ? 2 : 0;
+    }
+    TMFG_WT(1);
+    // (4) bounds, next positions, cached starts
+    float bound[3];
+    bool exhausted = false, skipping = false;
+#pragma unroll
     for (int t = 0; t < 3; ++t) {
-      if (ok[t]) {
-        const uint64_t kt = cand_key(g[t], id[t]);
-        k = kt > k ? kt : k;
-      }
+      bound[t] = -INFINITY;
       if (skip[t]) {
-        const uint64_t msk = __ballot(ok[t]);
-        if (msk) {
-          skip[t] = false;
-          np[t] = p[t] + r * kWave + (int)__builtin_ctzll(msk);
+        skipping = true;
+        continue;
+      }
+      const int end = (pos[t] & ~(kScan - 1)) + kSpan;
+      if (!tight[t]) {
+        const uint64_t any = __ballot(um[t] != 0) & gmask;
+        if (any) {
+          tight[t] = true;
+          newp[t] = __shfl(q[t] + (int)__builtin_ctz(um[t] | 0x100u), (int)__builtin_ctzll(any), kWave);
         } else {
-          np[t] = min(p[t] + (r + 1) * kWave, m);
+          newp[t] = end < m ? end : m;
+        }
+      }
+      if (seen[t] > kCand) {
+        // bound: the first entry not evaluated; resume there
+        const uint64_t own = __ballot(bl[t] >= 0) & gmask;
+        const int l = (int)__builtin_ctzll(own);
+        const int j = bl[t] & (kScan - 1);
+        const float bv = (j == 0) ? val[t][0] : (j == 1) ? val[t][1] : (j == 2) ? val[t][2] : val[t][3];
+        bound[t] = __shfl(bv, l, kWave);
+        pos[t] = __shfl(q[t] + j, l, kWave);
+      } else if (end >= m) {
+        exhausted = true;                        // the list is used up: nothing unseen
+        pos[t] = m;
+      } else {
+        bound[t] = __shfl(val[t][kScan - 1], gbase + kGroup - 1, kWave);   // last position scanned
+        pos[t] = end;
+        skip[t] = seen[t] == 0;                  // a fully inserted stretch: scan ahead wide
+      }
+    }
+    k = group_max_u64(k);
+    best = k > best ? k : best;
+    const float T = (bound[0] + bound[1]) + bound[2];
+    // A list being skipped has no bound this round; only exhaustion can end the walk then.
+    done = exhausted || (!skipping && best != 0 && (uint32_t)(best >> 32) > ord_f32(T));
+    TMFG_WT(2);
+    // (5) wide scans, one list at a time, for lists in a fully inserted stretch
+    if (!done && (skip[0] || skip[1] || skip[2])) {
+      ++*skips;
+#pragma unroll
+      for (int t = 0; t < 3; ++t) {
+        if (!skip[t]) continue;
+        uint4 sv[kSkipLoads];
+#pragma unroll
+        for (int w = 0; w < kSkipLoads; ++w) {
+          const int qs = (pos[t] & ~7) + (w * kGroup + gl) * 8;
+          sv[w] = *(const uint4*)(P.idx + (size_t)x3[t] * ldi + min(qs, ldi - 8));
+        }
+        int fp = 0x7fffffff;
+#pragma unroll
+        for (int w = 0; w < kSkipLoads; ++w) {
+          const int qs = (pos[t] & ~7) + (w * kGroup + gl) * 8;
+          const uint32_t wd[4] = {sv[w].x, sv[w].y, sv[w].z, sv[w].w};
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+            const int p = qs + j;
+            const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
+            fp = ok ? min(fp, p) : fp;
+          }
+        }
+        const int f = group_min_i32(fp);
+        const int end = (pos[t] & ~7) + kSkipLoads * kGroup * 8;
+        if (f != 0x7fffffff) {
+          pos[t] = f;
+          skip[t] = false;
+          if (!tight[t]) {
+            tight[t] = true;
+            newp[t] = f;
+          }
+        } else {
+          pos[t] = end < m ? end : m;
+          if (!tight[t]) newp[t] = pos[t];
+          if (end >= m) done = true;             // nothing uninserted is left in this list
         }
       }
     }
-    k = wave_max_u64(k);
-    best = k > best ? k : best;
-    const bool exhausted = p[0] + (r + 1) * kWave >= m || p[1] + (r + 1) * kWave >= m ||
-                           p[2] + (r + 1) * kWave >= m;
-    const float T = (last[0] + last[1]) + last[2];
-    done = exhausted || (best != 0 && (uint32_t)(best >> 32) > ord_f32(T));
+    TMFG_WT(3);
   }
-  if (lane == 0) {
+  if (gl == 0) {
 #pragma unroll
     for (int t = 0; t < 3; ++t)
-      if (np[t] > p[t]) ptr[x3[t]] = (uint16_t)np[t];
+      if (newp[t] > (int)ptr[x3[t]]) ptr[x3[t]] = (uint16_t)newp[t];
   }
+#undef TMFG_WT
   *rounds += r;
+  *gathers += ng;
   best_out = best;
   return done;
 }
 
 __device__ __forceinline__ uint64_t rec_key(const uint4& r) { return ((uint64_t)r.x << 32) | r.y; }
+__device__ __forceinline__ int rec_face(const uint4& r) { return 0xffff - (int)(r.y >> 16); }
+__device__ __forceinline__ int rec_vertex(const uint4& r) { return (int)(r.y & 0xffffu); }
 
 }  // namespace
 
@@ -197,22 +412,68 @@ __host__ __device__ inline LdsLayout lds_layout(int n) {
   L.total = L.off_ptr + ((size_t)n * 2 + 15) / 16 * 16;
   return L;
 }
+
+__device__ __forceinline__ uint4 make_rec(const Work& w) {
+  const uint64_t k = w.best;                          // low 16 bits: 0xffff - u
+  uint4 rec;
+  rec.x = (uint32_t)(k >> 32);
+  // key word: face id (inverted, so a lower id ranks higher) and the vertex; a face with no
+  // candidate left (after the last insertion) gets an all-zero key
+  rec.y = k ? ((uint32_t)(0xffff - w.f) << 16) | (0xffffu - (uint32_t)(k & 0xffffu)) : 0u;
+  rec.z = (uint32_t)w.a | ((uint32_t)w.b << 16);
+  rec.w = (uint32_t)w.c;
+  return rec;
+}
+
+// Wave 0: append to sel[] every chunk whose maximum record is stale (vertex inserted) and
+// ranks above `floor`, other than the chunks already listed. Returns the new length.
+__device__ int select_stale_chunks(const uint4* cmax, int nchunk, const uint32_t* bits, uint64_t floor,
+                                   int* sel, int cnt, int lane) {
+  const int given = cnt;
+  for (int ch0 = 0; ch0 < nchunk; ch0 += kWave) {
+    const int ch = ch0 + lane;
+    bool pick = false;
+    if (ch < nchunk) {
+      const uint4 r = cmax[ch];
+      const uint64_t k = rec_key(r);
+      pick = k > floor && is_ins(bits, rec_vertex(r));
+      for (int q = 0; q < given; ++q) pick &= sel[q] != ch;
+    }
+    const uint64_t msk = __ballot(pick);
+    if (pick) {
+      const int slot = cnt + (int)__popcll(msk & ((1ull << lane) - 1));
+      if (slot < kMaxSel) sel[slot] = ch;
+    }
+    cnt += (int)__popcll(msk);
+  }
+  return cnt < kMaxSel ? cnt : kMaxSel;
+}
+
+__device__ __forceinline__ uint64_t clock_ticks() { return wall_clock64(); }
 }  // namespace
 
 __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  __shared__ Work work[kWaves];
-  __shared__ int s_nwork, s_ins, s_F, s_stop, s_seed[4];
+  __shared__ Work work[kMaxWork];
+  __shared__ int sel[kMaxSel];
+  __shared__ GroupBuf gbuf[kGroups];
+  __shared__ uint4 s_crec[kMaxSel][kWave];       // the loaded chunk records
+  __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
+  __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4];
+  __shared__ uint64_t s_floor;
   __shared__ uint64_t s_part[kWaves];
   __shared__ int s_vpart[kWaves];
 
   const int n = P.n;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int gl = lane & (kGroup - 1), gbase = lane & ~(kGroup - 1);
+  const int gid = tid / kGroup;                              // face-walk group of this lane
   const LdsLayout LL = lds_layout(n);
   uint4* cmax = (uint4*)(smem + LL.off_cmax);
   uint32_t* bits = (uint32_t*)(smem + LL.off_bits);
   uint16_t* ptr = (uint16_t*)(smem + LL.off_ptr);
   const int nf = 2 * n - 4;
+  const uint64_t t_start = clock_ticks();
 
   // Errors raised by the kernels that produced W stop the build here.
   const uint32_t fl = *P.flags;
@@ -279,34 +540,108 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
     for (int f = 0; f < 4; ++f) {
       int x = tri[f][0], y = tri[f][1], z = tri[f][2];
       sort3(x, y, z);
-      work[f].f = f; work[f].a = x; work[f].b = y; work[f].c = z;
-      work[f].best = 0; work[f].sweep = 0;
+      work[f] = Work{f, x, y, z, 0, 0};
     }
     s_nwork = 4;
+    s_nnew = 4;
+    sel[0] = 0;
+    s_nsel = 1;
+    s_floor = ~0ull;
     s_ins = 4;
     s_F = 4;
     s_stop = 0;
+    s_nsweep = 0;
+    s_bmax = 0;
   }
   __syncthreads();
 
-  int walk_rounds = 0, stale_recomputes = 0, sweeps = 0, phases = 0, since_insert = 0;
+  // Counters (tmfg_plan_stats): kept in LDS so that they hold no registers in the loop.
+  //   [0] stale recomputes [1] walk rounds [2] sweeps [3] phases [4] walk batches
+  //   [5..9] ticks in select/load/walk/sweep/publish [11] W reads [12] critical rounds
+  //   [13] walks >= 4 rounds [14] walks >= 16 rounds [15] skip scans
+  __shared__ unsigned long long s_cnt[16];
+  __shared__ unsigned long long s_wt[4];         // walk sub-step ticks of group 0 (diagnostics)
+  __shared__ int s_since_insert;
+  __shared__ unsigned long long s_t0;
+  if (tid < 16) s_cnt[tid] = 0;
+  if (tid < 4) s_wt[tid] = 0;
+  if (tid == 0) {
+    s_since_insert = 0;
+    s_t0 = clock_ticks();
+  }
+  __syncthreads();
+#define TMFG_LAP(slot)                    \
+  if (tid == 0) {                         \
+    const uint64_t t1_ = clock_ticks();   \
+    s_cnt[slot] += t1_ - s_t0;            \
+    s_t0 = t1_;                           \
+  }
   for (;;) {
-    const int nwork = s_nwork;
+    // Phase B0: load the records of the queued chunks (one wave per chunk, one record per
+    // lane). Each record is linked to the work item that will replace it: a new face, or a
+    // stale record ranked above the floor, which is queued for recomputation.
+    const int nsel = s_nsel, nnew = s_nnew;
+    const uint64_t floor = s_floor;
+    for (int sl = wave; sl < nsel; sl += kWaves) {
+      const int f = sel[sl] * 64 + lane;
+      uint4 crec = make_uint4(0, 0, 0, 0);
+      int link = -1;
+      if (f < nf) crec = P.frec[f];
+      for (int q = 0; q < nnew; ++q)
+        if (work[q].f == f) link = q;
+      if (link < 0 && s_ins < n) {
+        const uint64_t k = rec_key(crec);
+        if (k != 0 && k > floor && is_ins(bits, rec_vertex(crec))) {
+          const int slot = atomicAdd(&s_nwork, 1);
+          if (slot < kMaxWork) {
+            work[slot] = Work{f, (int)(crec.z & 0xffffu), (int)(crec.z >> 16), (int)crec.w, 0, 0};
+            link = slot;
+          }
+        }
+      }
+      s_crec[sl][lane] = crec;
+      s_link[sl][lane] = (int16_t)link;
+    }
+    __syncthreads();
+    TMFG_LAP(6);
+    const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
+    if (tid == 0) s_cnt[0] += nwork - nnew;
     const bool have_cand = s_ins < n;
-    // Phase B: best pair of every face in the work list, one wave per face.
-    if (wave < nwork) {
-      Work& w = work[wave];
-      uint64_t best = 0;
-      bool ok = true;
-      if (have_cand) ok = walk_face(P, bits, ptr, w.a, w.b, w.c, best, lane, &walk_rounds);
-      if (lane == 0) {
-        w.best = best;
-        w.sweep = ok ? 0 : 1;
+    // Phase B: best pair of every queued face, one group of kGroup lanes per face.
+    for (int base = 0; base < nwork; base += kGroups) {
+      if (tid == 0) s_cnt[4] += 1;
+      const int item = base + gid;
+      if (item < nwork) {
+        Work& w = work[item];
+        uint64_t best = 0;
+        bool ok = true;
+        int rw = 0, gw = 0, sw = 0;
+        if (have_cand)
+          ok = walk_face(P, bits, ptr, gbuf[gid], w.a, w.b, w.c, gl, gbase, best, &rw, &gw, &sw,
+                         (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
+        // per-lane W reads, summed over the group
+        for (int off = kGroup / 2; off >= 1; off >>= 1) gw += __shfl_xor(gw, off, kWave);
+        if (gl == 0) {
+          w.best = best;
+          w.sweep = ok ? 0 : 1;
+          if (!ok) atomicAdd(&s_nsweep, 1);
+          atomicMax(&s_bmax, rw);
+          atomicAdd(&s_cnt[1], (unsigned long long)rw);
+          atomicAdd(&s_cnt[11], (unsigned long long)gw);
+          atomicAdd(&s_cnt[15], (unsigned long long)sw);
+          if (rw >= 4) atomicAdd(&s_cnt[13], 1ull);
+          if (rw >= 16) atomicAdd(&s_cnt[14], 1ull);
+        }
       }
     }
     __syncthreads();
+    if (tid == 0) {
+      s_cnt[12] += s_bmax;
+      s_bmax = 0;
+    }
+    TMFG_LAP(7);
     // Phase B2: faces whose walk gave up are swept by the whole workgroup, one at a time.
-    for (int q = 0; q < nwork; ++q) {
+    for (int q = 0; s_nsweep && q < nwork; ++q) {
       if (!work[q].sweep) continue;
       const int a = work[q].a, b = work[q].b, c = work[q].c;
       const float* Wa = P.W + (size_t)a * n;
@@ -327,43 +662,28 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
         for (int w = 1; w < kWaves; ++w) k = s_part[w] > k ? s_part[w] : k;
         work[q].best = k;
         work[q].sweep = 0;
-        ++sweeps;
+        s_cnt[2] += 1;
       }
       __syncthreads();
     }
-    // Phase B3: publish the new face records.
-    if (tid < nwork) {
-      const Work& w = work[tid];
-      const uint64_t k = w.best;                          // low 16 bits: 0xffff - u
-      uint4 rec;
-      rec.x = (uint32_t)(k >> 32);
-      // key word: face id (inverted, so a lower id ranks higher) and the vertex; a face
-      // with no candidate left (after the last insertion) gets an all-zero key
-      rec.y = k ? ((uint32_t)(0xffff - w.f) << 16) | (0xffffu - (uint32_t)(k & 0xffffu)) : 0u;
-      rec.z = (uint32_t)w.a | ((uint32_t)w.b << 16);
-      rec.w = (uint32_t)w.c;
-      P.frec[w.f] = rec;
-    }
-    __threadfence_block();
-    __syncthreads();
-    // Phase C: refresh the chunk maxima of the chunks touched this phase.
-    if (wave < nwork) {
-      const int ch = work[wave].f >> 6;
-      bool first = true;
-      for (int q = 0; q < wave; ++q) first &= (work[q].f >> 6) != ch;
-      if (first) {
-        const int f = ch * 64 + lane;
-        const uint4 r = f < nf ? P.frec[f] : make_uint4(0, 0, 0, 0);
-        const uint64_t k = rec_key(r);
-        const uint64_t mx = wave_max_u64(k);
-        const uint64_t msk = __ballot(k == mx);
-        if (lane == (int)__builtin_ctzll(msk)) cmax[ch] = r;
-      }
+    TMFG_LAP(8);
+    // Phase B3: publish the new face records. Phase C: rebuild the maxima of the loaded
+    // chunks from the records held in registers, with the recomputed ones substituted.
+    if (tid == 0) s_nsweep = 0;
+    if (tid < nwork) P.frec[work[tid].f] = make_rec(work[tid]);
+    for (int sl = wave; sl < nsel; sl += kWaves) {
+      const int link = s_link[sl][lane];
+      const uint4 crec = link >= 0 ? make_rec(work[link]) : s_crec[sl][lane];
+      const uint64_t k = rec_key(crec);
+      const uint64_t mx = wave_max_u64(k);
+      const uint64_t msk = __ballot(k == mx);
+      if (lane == (int)__builtin_ctzll(msk)) cmax[sel[sl]] = crec;
     }
     __syncthreads();
+    TMFG_LAP(9);
     if (s_ins >= n || s_stop) break;
     // Phase A: select (wave 0).
-    ++phases;
+    if (tid == 0) s_cnt[3] += 1;
     if (wave == 0) {
       uint64_t k1 = 0, kf = 0;
       for (int ch = lane; ch < LL.nchunk; ch += kWave) {
@@ -371,19 +691,19 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
         const uint64_t k = rec_key(r);
         if (!k) continue;
         k1 = k > k1 ? k : k1;
-        const int u = (int)(r.y & 0xffffu);
-        if (!is_ins(bits, u)) kf = k > kf ? k : kf;
+        if (!is_ins(bits, rec_vertex(r))) kf = k > kf ? k : kf;
       }
       k1 = wave_max_u64(k1);
       kf = wave_max_u64(kf);
       const int f1 = 0xffff - (int)((uint32_t)k1 >> 16);
       if (k1 != 0 && k1 == kf) {
-        // Fresh maximum: insert.
+        // Fresh maximum: insert its vertex.
+        const uint4 r = cmax[f1 >> 6];
+        const int u = rec_vertex(r);
+        const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
+        const int F = s_F;
         if (lane == 0) {
-          const uint4 r = cmax[f1 >> 6];
-          const int u = (int)(r.y & 0xffffu);
-          const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
-          const int ins = s_ins, st = ins - 4, F = s_F;
+          const int ins = s_ins, st = ins - 4;
           P.order[ins] = u;
           int32_t* e = P.edges + 2 * (6 + 3 * st);
           e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
@@ -391,68 +711,73 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
           sp[0] = f1; sp[1] = x; sp[2] = y; sp[3] = z;
           P.step_gain[st] = unord_f32(r.x);
           bits[u >> 5] |= 1u << (u & 31);
-          int t0 = u, t1 = x, t2 = y;
-          sort3(t0, t1, t2);
-          work[0] = Work{f1, t0, t1, t2, 0, 0};
-          t0 = u; t1 = y; t2 = z;
-          sort3(t0, t1, t2);
-          work[1] = Work{F, t0, t1, t2, 0, 0};
-          t0 = u; t1 = x; t2 = z;
-          sort3(t0, t1, t2);
-          work[2] = Work{F + 1, t0, t1, t2, 0, 0};
-          s_nwork = 3;
+          int t0_ = u, t1_ = x, t2_ = y;
+          sort3(t0_, t1_, t2_);
+          work[0] = Work{f1, t0_, t1_, t2_, 0, 0};
+          t0_ = u; t1_ = y; t2_ = z;
+          sort3(t0_, t1_, t2_);
+          work[1] = Work{F, t0_, t1_, t2_, 0, 0};
+          t0_ = u; t1_ = x; t2_ = z;
+          sort3(t0_, t1_, t2_);
+          work[2] = Work{F + 1, t0_, t1_, t2_, 0, 0};
           s_ins = ins + 1;
           s_F = F + 2;
+          s_nwork = 3;
+          s_nnew = 3;
+          sel[0] = f1 >> 6;
+          sel[1] = F >> 6;       // F is even, so F and F + 1 share a chunk
         }
-        since_insert = 0;
-      } else if (k1 == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        // The chunks of the three new faces are reloaded. Faces whose cached vertex was u
+        // are stale now; the chunks whose maximum is stale and ranks above the best fresh
+        // record that remains are loaded too, and every stale record in them ranked above
+        // that floor is recomputed along with the new faces.
+        int ns = (F >> 6) != (f1 >> 6) ? 2 : 1;
+        uint64_t kf2 = ~0ull;
+        if (s_ins < n) {
+          kf2 = 0;
+          for (int ch = lane; ch < LL.nchunk; ch += kWave) {
+            const uint4 q = cmax[ch];
+            const uint64_t k = rec_key(q);
+            if (k && !is_ins(bits, rec_vertex(q))) kf2 = k > kf2 ? k : kf2;
+          }
+          kf2 = wave_max_u64(kf2);
+          ns = select_stale_chunks(cmax, LL.nchunk, bits, kf2, sel, ns, lane);
+        }
+        if (lane == 0) {
+          s_nsel = ns;
+          s_floor = kf2;
+          s_since_insert = 0;
+        }
+      } else if (k1 == 0 || s_since_insert + 1 > nf + 8) {
         if (lane == 0) {
           *P.status = 8;
           s_stop = 1;
           s_nwork = 0;
+          s_nnew = 0;
+          s_nsel = 0;
         }
       } else {
-        // Stale maximum: recompute every stale chunk maximum ranked above the best fresh
-        // record (the top one first), up to one per wave.
-        if (++since_insert > nf + 8) {
-          if (lane == 0) {
-            *P.status = 8;
-            s_stop = 1;
-            s_nwork = 0;
-          }
-        } else {
-          if (lane == 0) {
-            const uint4 r = cmax[f1 >> 6];
-            work[0] = Work{f1, (int)(r.z & 0xffffu), (int)(r.z >> 16), (int)r.w, 0, 0};
-          }
-          int cnt = 1;
-          for (int ch0 = 0; ch0 < LL.nchunk; ch0 += kWave) {
-            const int ch = ch0 + lane;
-            bool pick = false;
-            uint4 r = make_uint4(0, 0, 0, 0);
-            if (ch < LL.nchunk) {
-              r = cmax[ch];
-              const uint64_t k = rec_key(r);
-              const int u = (int)(r.y & 0xffffu);
-              pick = k > kf && k != k1 && is_ins(bits, u);
-            }
-            const uint64_t msk = __ballot(pick);
-            if (pick) {
-              const int slot = cnt + (int)__popcll(msk & ((1ull << lane) - 1));
-              if (slot < kWaves) {
-                const int f = 0xffff - (int)(r.y >> 16);
-                work[slot] = Work{f, (int)(r.z & 0xffffu), (int)(r.z >> 16), (int)r.w, 0, 0};
-              }
-            }
-            cnt += (int)__popcll(msk);
-          }
-          if (lane == 0) s_nwork = cnt < kWaves ? cnt : kWaves;
-          stale_recomputes += cnt < kWaves ? cnt : kWaves;
+        // Stale maximum: load every chunk whose maximum is stale and ranks above the best
+        // fresh record (the top one first) and recompute their stale records above it.
+        if (lane == 0) sel[0] = f1 >> 6;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        const int ns = select_stale_chunks(cmax, LL.nchunk, bits, kf, sel, 1, lane);
+        if (lane == 0) {
+          s_nsel = ns;
+          s_floor = kf;
+          s_nwork = 0;
+          s_nnew = 0;
+          s_since_insert += 1;
         }
       }
     }
     __syncthreads();
+    TMFG_LAP(5);
   }
+#undef TMFG_LAP
 
   // Final faces, ascending triples in face-id order.
   __syncthreads();
@@ -462,17 +787,15 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
     P.faces[3 * f + 1] = (int)(r.z >> 16);
     P.faces[3 * f + 2] = (int)r.w;
   }
-  if (lane == 0) s_vpart[wave] = walk_rounds;
   __syncthreads();
   if (tid == 0) {
     if (!s_stop) *P.status = 0;
     if (P.stats) {
-      int wr = 0;
-      for (int w = 0; w < kWaves; ++w) wr += s_vpart[w];
-      P.stats[0] = stale_recomputes;
-      P.stats[1] = wr;
-      P.stats[2] = sweeps;
-      P.stats[3] = phases;
+      for (int i = 0; i < 16; ++i) {
+        const unsigned long long v = (i == 10) ? clock_ticks() - t_start : s_cnt[i];
+        P.stats[i] = (int32_t)(v > 0x7fffffffull ? 0x7fffffffull : v);
+      }
+      for (int i = 0; i < 4; ++i) P.stats[16 + i] = (int32_t)(s_wt[i] > 0x7fffffffull ? 0x7fffffffull : s_wt[i]);
     }
   }
 }

@@ -18,7 +18,8 @@
 //     precede it by (key, id), which is its exact position: the composite key is unique,
 //     so the outcome is deterministic even though the scatter is not;
 //  5. larger buckets (many exactly equal similarities) are bitonic-sorted by one wave each;
-//  6. the ids are written out with 16-byte stores.
+//  6. the ids are written out with 16-byte stores, and, when asked for, the similarities in
+//     the same order (W[v][u] as float32, -0.0 written as +0.0).
 #include "common.h"
 #include "internal.h"
 
@@ -59,8 +60,8 @@ __device__ void wave_bitonic(uint32_t* k, uint16_t* id, int sz, int lane) {
 
 template <int BLOCK, int EPT>
 __global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restrict__ W, int n,
-                                                          uint16_t* __restrict__ idx, int64_t ldi,
-                                                          int sub_log2) {
+                                                          uint16_t* __restrict__ idx, float* __restrict__ vals,
+                                                          int64_t ldi, int sub_log2) {
   constexpr int NWAVE = BLOCK / kWave;
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   __shared__ uint32_t red_lo[NWAVE], red_hi[NWAVE];
@@ -217,8 +218,14 @@ __global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restric
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < EPT; ++e)
-    if (fin[e] >= 0) ids[fin[e]] = (uint16_t)(e * BLOCK + tid);
-  for (int i = m + tid; i < m_al; i += BLOCK) ids[i] = 0xffff;
+    if (fin[e] >= 0) {
+      ids[fin[e]] = (uint16_t)(e * BLOCK + tid);
+      keys[fin[e]] = dk[e];
+    }
+  for (int i = m + tid; i < m_al; i += BLOCK) {
+    ids[i] = 0xffff;
+    keys[i] = 0xff800000u;              // -inf
+  }
   __syncthreads();
 
   // 5. large buckets
@@ -233,6 +240,13 @@ __global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restric
   uint4* dst = (uint4*)(idx + (size_t)v * ldi);
   const uint4* src = (const uint4*)ids;
   for (int i = tid; i < m_al / 8; i += BLOCK) dst[i] = src[i];
+  if (vals) {
+    float4* vdst = (float4*)(vals + (size_t)v * ldi);
+    for (int i = tid; i < m_al / 4; i += BLOCK) {
+      const uint4 k = ((const uint4*)keys)[i];
+      vdst[i] = make_float4(unord_f32(~k.x), unord_f32(~k.y), unord_f32(~k.z), unord_f32(~k.w));
+    }
+  }
 }
 
 namespace {
@@ -251,28 +265,28 @@ size_t sort_lds_bytes(int n, int sub_log2) {
   return (size_t)m_al * 6 + (size_t)NB * 4 + (size_t)S * 4;
 }
 template <int BLOCK, int EPT>
-hipError_t launch_sort_t(const float* W, int n, uint16_t* idx, int64_t ldi, hipStream_t s) {
+hipError_t launch_sort_t(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
   const int sl = sort_sub_log2(n);
   const size_t lds = sort_lds_bytes(n, sl);
   auto k = sort_rows_kernel<BLOCK, EPT>;
   hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(n), dim3(BLOCK), lds, s, W, n, idx, ldi, sl);
+  hipLaunchKernelGGL(k, dim3(n), dim3(BLOCK), lds, s, W, n, idx, vals, ldi, sl);
   return hipGetLastError();
 }
 }  // namespace
 
 int64_t sort_row_stride(int n) { return round_up(n - 1 > 0 ? n - 1 : 1, 8); }
 
-hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, int64_t ldi, hipStream_t s) {
-  if (n <= 256) return launch_sort_t<256, 1>(W, n, idx, ldi, s);
-  if (n <= 1024) return launch_sort_t<256, 4>(W, n, idx, ldi, s);
-  if (n <= 2048) return launch_sort_t<512, 4>(W, n, idx, ldi, s);
-  if (n <= 4096) return launch_sort_t<1024, 4>(W, n, idx, ldi, s);
-  if (n <= 8192) return launch_sort_t<1024, 8>(W, n, idx, ldi, s);
-  if (n <= 12288) return launch_sort_t<1024, 12>(W, n, idx, ldi, s);
-  if (n <= 16384) return launch_sort_t<1024, 16>(W, n, idx, ldi, s);
-  return launch_sort_t<1024, 20>(W, n, idx, ldi, s);
+hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
+  if (n <= 256) return launch_sort_t<256, 1>(W, n, idx, vals, ldi, s);
+  if (n <= 1024) return launch_sort_t<256, 4>(W, n, idx, vals, ldi, s);
+  if (n <= 2048) return launch_sort_t<512, 4>(W, n, idx, vals, ldi, s);
+  if (n <= 4096) return launch_sort_t<1024, 4>(W, n, idx, vals, ldi, s);
+  if (n <= 8192) return launch_sort_t<1024, 8>(W, n, idx, vals, ldi, s);
+  if (n <= 12288) return launch_sort_t<1024, 12>(W, n, idx, vals, ldi, s);
+  if (n <= 16384) return launch_sort_t<1024, 16>(W, n, idx, vals, ldi, s);
+  return launch_sort_t<1024, 20>(W, n, idx, vals, ldi, s);
 }
 
 }  // namespace tmfg

@@ -45,7 +45,7 @@ def test_host_side_argument_errors():
     assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1 << 9) == 1
     assert lib.tmfg_build(None, None, None) == 1
     assert lib.tmfg_correlation(None, None, 10, 10, None, None, None) == 1
-    assert lib.tmfg_sort_rows(None, None, 10, None, 16, None) == 1
+    assert lib.tmfg_sort_rows(None, None, 10, None, None, 16, None) == 1
     assert lib.tmfg_seed(None, None, 10, None, None, None) == 1
     assert lib.tmfg_face_sweep(None, None, 10, None, 1, None, None, None, None) == 1
     assert lib.tmfg_plan_destroy(None) == 0

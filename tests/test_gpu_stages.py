@@ -13,15 +13,19 @@ pytestmark = pytest.mark.gpu
 
 def _sort_check(W: np.ndarray, rows=None):
     n = W.shape[0]
-    idx = tm.sort_rows(to_dev(W))
+    idx, vals = tm.sort_rows(to_dev(W), with_values=True)
     torch.cuda.synchronize()
     got = uint16_rows(idx, n)
+    gv = vals.cpu().numpy()[:, : n - 1]
     rows = range(n) if rows is None else rows
     for v in rows:
         ref = oracle.sorted_row(W, v)
         if not np.array_equal(got[v], ref):
             bad = np.flatnonzero(got[v] != ref)[:5]
             raise AssertionError(f"row {v} differs at {bad.tolist()}")
+        # the values carried beside the ids are W[v][ids] with -0.0 written as +0.0
+        expect = W[v, ref] + np.float32(0.0)
+        assert gv[v].tobytes() == expect.tobytes(), f"row {v} values"
 
 
 @pytest.mark.parametrize("n", [4, 5, 63, 64, 65, 200, 257, 1000, 1025, 2049, 4097])
