@@ -32,7 +32,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--batch", type=int, default=512, help="instances in the c4 batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1500)
     return ap.parse_args()
@@ -103,11 +104,68 @@ def _lazy_prefix(W: np.ndarray, k: int) -> None:
             heapq.heappush(heap, (-float(g2), nf, u2))
 
 
+def bench_batch(args):
+    """512 independent instances (n log-uniform in [64, 4096], L uniform in [64, 512]) in one
+    graph replay, against the same instances built one per launch."""
+    import torch
+    import paper_2408_09399_amd as tm
+    from paper_2408_09399_amd import synth
+    inst = synth.config_c4(args.batch)
+    dev = torch.device("cuda:0")
+    Xs = [torch.from_numpy(s.X).to(dev) for s in inst]
+    batch = tm.Batch([("X", x) for x in Xs])
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        batch.run(stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.run(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    bad = [i for i, r in enumerate(batch.results) if int(r.status.item()) != 0]
+    if bad:
+        print(json.dumps({"error": f"batch instances failed: {bad[:5]}"}))
+        sys.exit(1)
+    # the same instances, one build (one launch sequence) each, back to back on one plan
+    n_max = max(s.X.shape[0] for s in inst)
+    L_max = max(s.X.shape[1] for s in inst)
+    plan = tm.Plan(n_max, L_max)
+    outs = [tm.alloc_result(x.shape[0], dev) for x in Xs]
+    for x, o in zip(Xs[:8], outs[:8]):
+        tm.build(X=x, plan=plan, out=o, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for x, o in zip(Xs, outs):
+        tm.build(X=x, plan=plan, out=o, stream=stream)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    insertions = sum(s.X.shape[0] - 4 for s in inst)
+    per = wall / args.steps
+    out = {
+        "metric": "batched builds/s (512 uneven instances per graph replay)",
+        "value": round(len(inst) / per, 2), "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(per * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{len(inst)} planted-cluster instances, n log-uniform in [64, 4096], "
+                               f"L uniform in [64, 512]", "instances": len(inst),
+                   "sum_n": int(sum(s.X.shape[0] for s in inst))},
+        "insertions_per_s": round(insertions / per, 1),
+        "plain_one_per_launch": {"seconds": round(plain, 3), "builds_per_s": round(len(inst) / plain, 2)},
+        "speedup_vs_plain": round(plain / per, 2),
+    }
+    plan.close()
+    batch.close()
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
         sys.exit(2)
+    if args.config == "c4":
+        return bench_batch(args)
     import torch
     import paper_2408_09399_amd as tm
 

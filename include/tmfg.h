@@ -61,13 +61,15 @@ typedef enum {
   TMFG_E_INTERNAL = 8     /* an internal consistency check failed on the device */
 } tmfg_status;
 
-/* Plan flags. */
+/* Plan and batch flags. */
 enum {
-  TMFG_NO_VALIDATE = 1u << 0, /* skip the finite / bitwise-symmetry check of a caller W */
-  TMFG_TIMING = 1u << 1       /* record per-phase HIP events (tmfg_plan_phase_ms) */
+  TMFG_NO_VALIDATE = 1u << 0,   /* skip the finite / bitwise-symmetry check of a caller W */
+  TMFG_TIMING = 1u << 1,        /* record per-phase HIP events (tmfg_plan_phase_ms) */
+  TMFG_BATCH_NO_GRAPH = 1u << 2 /* batch: launch the kernels directly instead of a graph */
 };
 
 typedef struct tmfg_plan_s* tmfg_plan;
+typedef struct tmfg_batch_s* tmfg_batch;
 
 /* One TMFG construction. Exactly one of X and W is non-NULL. */
 typedef struct {
@@ -117,6 +119,30 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    spent loading and ranking list entries, reading candidate similarities, updating
    bounds, and skip-scanning (diagnostics), [20..31] reserved. */
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
+
+/* ---- Batches: many independent builds in one graph replay ------------------------ */
+
+/* Prepare `count` builds (the jobs' sizes and buffers are fixed from now on): allocates
+   their scratch (tmfg_batch_footprint_bytes) and captures one hipGraph that runs every
+   phase as one grouped launch over all instances, and the insertion loops as one
+   persistent launch whose workgroups take instances largest first. Each instance gets the
+   result tmfg_build would give it, bit for bit. Flags: TMFG_NO_VALIDATE,
+   TMFG_BATCH_NO_GRAPH. */
+tmfg_status tmfg_batch_create(tmfg_batch* batch, const tmfg_job* jobs, int32_t count, uint32_t flags);
+
+/* Run (replay) the batch on `stream`; the inputs may change between runs, the buffers may
+   not. Each job's *status receives its own tmfg_status. */
+tmfg_status tmfg_batch_run(tmfg_batch batch, hipStream_t stream);
+
+/* Release a batch (waits for the device). NULL is a no-op. */
+tmfg_status tmfg_batch_destroy(tmfg_batch batch);
+
+/* Device bytes a batch over these jobs holds; 0 if a job is invalid. */
+size_t tmfg_batch_footprint_bytes(const tmfg_job* jobs, int32_t count, uint32_t flags);
+
+/* One-call form: builds (or reuses, when the job array is the same as the previous call's)
+   a batch kept by the plan, and runs it on `stream`. The plan's n_max does not limit it. */
+tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count, hipStream_t stream);
 
 /* ---- The stages of a build, callable on their own ------------------------------- */
 

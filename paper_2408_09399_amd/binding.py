@@ -22,6 +22,7 @@ STATUS = {
 }
 NO_VALIDATE = 1 << 0
 TIMING = 1 << 1
+BATCH_NO_GRAPH = 1 << 2
 
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -37,6 +38,11 @@ SIGNATURES = {
     "tmfg_sort_rows": (_I, [_P, _P, _I, _P, _P, ctypes.c_int64, _P]),
     "tmfg_seed": (_I, [_P, _P, _I, _P, _P, _P]),
     "tmfg_face_sweep": (_I, [_P, _P, _I, _P, _I, _P, _P, _P, _P]),
+    "tmfg_batch_create": (_I, [ctypes.POINTER(_P), _P, _I, ctypes.c_uint32]),
+    "tmfg_batch_run": (_I, [_P, _P]),
+    "tmfg_batch_destroy": (_I, [_P]),
+    "tmfg_batch_footprint_bytes": (ctypes.c_size_t, [_P, _I, ctypes.c_uint32]),
+    "tmfg_build_batch": (_I, [_P, _P, _I, _P]),
     "tmfg_status_string": (ctypes.c_char_p, [_I]),
     "tmfg_last_hip_error": (ctypes.c_int, []),
 }
@@ -281,3 +287,45 @@ def face_sweep(W, faces, inserted_words, plan: Optional[Plan] = None, stream=Non
     _check(_lib().tmfg_face_sweep(plan.handle, _ptr(W), n, _ptr(faces), F, _ptr(inserted_words),
                                   _ptr(bu), _ptr(bg), _stream(stream)), "tmfg_face_sweep")
     return bu, bg
+
+
+class Batch:
+    """Many independent builds prepared once and replayed as one graph.
+
+    `inputs` is a list of (kind, tensor) with kind "X" (series, (n, L)) or "W"
+    (similarity, (n, n)), float32 device tensors that stay alive with the batch; their
+    contents may change between runs. Results are allocated here, one Result per input.
+    """
+
+    def __init__(self, inputs, keep_w: bool = False, flags: int = 0):
+        import torch
+        self.inputs = list(inputs)
+        self.results = []
+        jobs = (Job * len(self.inputs))()
+        for i, (kind, t) in enumerate(self.inputs):
+            t = _need(t, torch.float32, kind)
+            n = t.shape[0]
+            res = alloc_result(n, t.device, keep_w)
+            self.results.append(res)
+            X, W = (t, None) if kind == "X" else (None, t)
+            jobs[i] = make_job(n, t.shape[1] if kind == "X" else 0, X, W, res)
+        self._jobs = jobs
+        h = ctypes.c_void_p()
+        _check(_lib().tmfg_batch_create(ctypes.byref(h), ctypes.cast(jobs, ctypes.c_void_p), len(self.inputs),
+                                        flags), "tmfg_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib().tmfg_batch_run(self._h, _stream(stream)), "tmfg_batch_run")
+        return self.results
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _check(_lib().tmfg_batch_destroy(self._h), "tmfg_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

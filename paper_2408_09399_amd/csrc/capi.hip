@@ -13,6 +13,13 @@ tmfg_status hip_fail(hipError_t e) {
   g_last_hip = (int)e;
   return TMFG_E_HIP;
 }
+
+}  // namespace
+
+extern "C" bool tmfg_batch_matches(tmfg_batch batch, const tmfg_job* jobs, int32_t count);
+void tmfg::record_hip_error(int e) { g_last_hip = e; }
+
+namespace {
 #define TMFG_HIP(call)                       \
   do {                                       \
     hipError_t e_ = (call);                  \
@@ -72,6 +79,7 @@ struct tmfg_plan_s {
   int32_t* stats = nullptr;
   hipEvent_t ev[kPhaseEvents] = {};
   bool timed = false;
+  tmfg_batch batch = nullptr;   // the last batch built through tmfg_build_batch
   int wall_khz = 100000;   // device wall-clock counter rate
 };
 
@@ -89,6 +97,7 @@ void plan_free(tmfg_plan p) {
   hipFree(p->stats);
   for (auto& e : p->ev)
     if (e) hipEventDestroy(e);
+  if (p->batch) tmfg_batch_destroy(p->batch);
   delete p;
 }
 
@@ -141,9 +150,11 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint
   *plan = nullptr;
   if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING)) return TMFG_E_INVALID;
   if (n_max < tmfg::kMinN || n_max > tmfg::kMaxN || L_max < 2) return TMFG_E_SIZE;
+  hipError_t e = tmfg::init_attributes_once();
+  if (e != hipSuccess) return hip_fail(e);
   tmfg_plan p = new (std::nothrow) tmfg_plan_s();
   if (!p) return TMFG_E_NOMEM;
-  hipError_t e = hipGetDevice(&p->device);
+  e = hipGetDevice(&p->device);
   if (e != hipSuccess) {
     delete p;
     return hip_fail(e);
@@ -236,6 +247,19 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
   record(plan, 4, stream);
   plan->timed = (plan->flags & TMFG_TIMING) != 0;
   return TMFG_OK;
+}
+
+tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count, hipStream_t stream) {
+  if (!plan || !jobs || count <= 0) return TMFG_E_INVALID;
+  if (!tmfg_batch_matches(plan->batch, jobs, count)) {
+    if (plan->batch) {
+      tmfg_batch_destroy(plan->batch);
+      plan->batch = nullptr;
+    }
+    const tmfg_status st = tmfg_batch_create(&plan->batch, jobs, count, plan->flags & TMFG_NO_VALIDATE);
+    if (st != TMFG_OK) return st;
+  }
+  return tmfg_batch_run(plan->batch, stream);
 }
 
 tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]) {

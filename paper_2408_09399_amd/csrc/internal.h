@@ -50,3 +50,68 @@ hipError_t launch_loop(const LoopParams& p, hipStream_t s);
 size_t loop_lds_bytes(int n);
 
 }  // namespace tmfg
+
+namespace tmfg {
+
+// One instance of a batch, as the batched kernels see it (device memory).
+struct BatchJob {
+  int n, L, n_pad, L_pad;
+  int64_t ldi;
+  const float* X;          // series, or null when W is given
+  const float* W;          // the similarity matrix the build uses (caller's or scratch)
+  float* Wdst;             // where the correlation kernels write W (null for a caller W)
+  float* Z;
+  uint16_t* idx;
+  float* vals;
+  double* scores;
+  uint4* frec;
+  uint32_t* flags;
+  int32_t* order;
+  int32_t* edges;
+  int32_t* steps;
+  float* step_gain;
+  int32_t* faces;
+  int32_t* status;
+};
+
+// Grouped launches over the instances of a batch. Each takes a device list of job indices
+// and a device prefix array (prefix[i] = first unit of list[i], prefix[nlist] = total) of
+// the phase's work units: rows, tiles or columns; blocks find their job by binary search.
+hipError_t launch_batch_reset(BatchJob* jobs, int count, int* queue_head, hipStream_t s);
+hipError_t launch_batch_standardize(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                                    hipStream_t s);
+hipError_t launch_batch_gemm(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                             hipStream_t s);
+hipError_t launch_batch_validate(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                                 hipStream_t s);
+hipError_t launch_batch_seed(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                             hipStream_t s);
+// All instances in one sort launch share a size class (sort_class(n)); n_max is the
+// largest n among them.
+hipError_t launch_batch_sort(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                             int n_max, hipStream_t s);
+int sort_class(int n);
+// Persistent insertion loops: `grid` workgroups take instances from `order` (device array
+// of job indices, largest first) through the counter at *queue_head.
+hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
+                             int n_max, int32_t* stats, hipStream_t s);
+int corr_tiles(int n);                        // upper-triangular correlation tiles of n rows
+hipError_t sort_init_attributes();            // LDS limits of the kernels (set once)
+hipError_t loop_init_attributes();
+hipError_t init_attributes_once();            // both of the above, once per process
+hipError_t batch_loop_occupancy(int* per_cu, int n_max);   // loop workgroups per CU
+void record_hip_error(int e);                 // for tmfg_last_hip_error()
+int validate_tiles(int n);                    // 32x32 validation tiles of an n x n matrix
+
+// Binary search: the i in [0, nlist) with prefix[i] <= unit < prefix[i + 1].
+__device__ __forceinline__ int find_unit(const int* prefix, int nlist, int unit) {
+  int lo = 0, hi = nlist - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= unit) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace tmfg

@@ -452,8 +452,7 @@ __device__ int select_stale_chunks(const uint4* cmax, int nchunk, const uint32_t
 __device__ __forceinline__ uint64_t clock_ticks() { return wall_clock64(); }
 }  // namespace
 
-__global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+__device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ Work work[kMaxWork];
   __shared__ int sel[kMaxSel];
   __shared__ GroupBuf gbuf[kGroups];
@@ -800,13 +799,75 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
   }
 }
 
+__global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  run_loop(P, smem);
+}
+
+// Batched form: persistent workgroups take instances, largest first, from a shared counter;
+// each runs that instance's whole insertion loop. The counter is read by one thread and
+// every workgroup ends when the list is used up.
+__global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __restrict__ jobs,
+                                                            const int* __restrict__ order, int count,
+                                                            int* __restrict__ queue_head) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  __shared__ int s_job;
+  for (;;) {
+    if (threadIdx.x == 0) s_job = atomicAdd(queue_head, 1);
+    __syncthreads();
+    const int q = s_job;
+    __syncthreads();
+    if (q >= count) break;
+    const BatchJob& J = jobs[order[q]];
+    LoopParams P;
+    P.W = J.W;
+    P.n = J.n;
+    P.idx = J.idx;
+    P.vals = J.vals;
+    P.ldi = J.ldi;
+    P.scores = J.scores;
+    P.frec = J.frec;
+    P.flags = J.flags;
+    P.order = J.order;
+    P.edges = J.edges;
+    P.steps = J.steps;
+    P.step_gain = J.step_gain;
+    P.faces = J.faces;
+    P.status = J.status;
+    P.stats = nullptr;
+    run_loop(P, smem);
+    __syncthreads();
+  }
+}
+
 size_t loop_lds_bytes(int n) { return lds_layout(n).total; }
+
+hipError_t batch_loop_occupancy(int* per_cu, int n_max) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, batch_loop_kernel, kBlock, loop_lds_bytes(n_max));
+}
+
+hipError_t loop_init_attributes() {
+  const void* ks[2] = {(const void*)tmfg_loop_kernel, (const void*)batch_loop_kernel};
+  for (const void* k : ks) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, k);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
+                             int n_max, int32_t* stats, hipStream_t s) {
+  (void)stats;
+  const size_t lds = loop_lds_bytes(n_max);
+  hipLaunchKernelGGL(batch_loop_kernel, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
+  return hipGetLastError();
+}
 
 hipError_t launch_loop(const LoopParams& p, hipStream_t s) {
   const size_t lds = loop_lds_bytes(p.n);
-  hipError_t e = hipFuncSetAttribute((const void*)tmfg_loop_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)lds);
-  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(tmfg_loop_kernel, dim3(1), dim3(kBlock), lds, s, p);
   return hipGetLastError();
 }

@@ -9,17 +9,13 @@
 namespace tmfg {
 
 // ---------------------------------------------------------------------------------------
-// Standardisation: one wave per series. Mean and centred norm are accumulated in float64;
-// z is stored as float32 in a zero-padded (n_pad x L_pad) buffer so that the GEMM needs no
-// bounds checks. A series with non-finite values, or with all values equal (no Pearson
-// correlation exists), raises a flag.
+// Standardisation of one series by one wave. Mean and centred norm are accumulated in
+// float64; z is stored as float32 in a zero-padded (n_pad x L_pad) buffer so that the GEMM
+// needs no bounds checks. A series with non-finite values, or with all values equal (no
+// Pearson correlation exists), raises a flag.
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void standardize_kernel(const float* __restrict__ X, int n, int L,
-                                                          float* __restrict__ Z, int n_pad, int L_pad,
-                                                          uint32_t* __restrict__ flags) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (row >= n_pad) return;
+__device__ void standardize_row(const float* __restrict__ X, int n, int L, float* __restrict__ Z, int L_pad,
+                                uint32_t* __restrict__ flags, int row, int lane) {
   float* z = Z + (size_t)row * L_pad;
   if (row >= n) {
     for (int k = lane; k < L_pad; k += kWave) z[k] = 0.0f;
@@ -60,6 +56,14 @@ __global__ __launch_bounds__(256) void standardize_kernel(const float* __restric
   for (int k = lane; k < L_pad; k += kWave) z[k] = k < L ? (float)(((double)x[k] - mean) * inv) : 0.0f;
 }
 
+__global__ __launch_bounds__(256) void standardize_kernel(const float* __restrict__ X, int n, int L,
+                                                          float* __restrict__ Z, int n_pad, int L_pad,
+                                                          uint32_t* __restrict__ flags) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n_pad) return;
+  standardize_row(X, n, L, Z, L_pad, flags, row, threadIdx.x & 63);
+}
+
 // ---------------------------------------------------------------------------------------
 // W = Z Z^T with v_mfma_f32_32x32x2_f32.
 //
@@ -81,24 +85,15 @@ __global__ __launch_bounds__(256) void standardize_kernel(const float* __restric
 namespace {
 constexpr int BM = 128, BK = 32, LDA = BK + 2;  // LDS row stride in floats (pad for banks)
 constexpr int LDT = BM + 1;
+constexpr int kGemmSmem = BM * LDT;              // floats
 typedef float f16x __attribute__((ext_vector_type(16)));
 }  // namespace
 
 __device__ __forceinline__ float fix_corr(float v) { return fminf(fmaxf(v, -1.0f), 1.0f) + 0.0f; }
 
-__global__ __launch_bounds__(256, 2) void corr_gemm_kernel(const float* __restrict__ Z, int n, int L_pad,
-                                                           int nb, int tiles, int tiles_per_xcd,
-                                                           float* __restrict__ W) {
-  // Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous run of tiles
-  // (tiles in one block-row share their A operand, which then stays in that XCD's L2).
-  const int xcd = blockIdx.x & 7;
-  const int t = xcd * tiles_per_xcd + (blockIdx.x >> 3);
-  if (t >= tiles) return;
-  int bi, bj;
-  upper_tri_coords(t, nb, bi, bj);
+__device__ void gemm_tile(const float* __restrict__ Z, int n, int L_pad, float* __restrict__ W, int bi, int bj,
+                          float* smem) {
   const int i0 = bi * BM, j0 = bj * BM;
-
-  __shared__ __attribute__((aligned(16))) float smem[BM * LDT];
   float* As = smem;
   float* Bs = smem + BM * LDA;
 
@@ -182,6 +177,48 @@ __global__ __launch_bounds__(256, 2) void corr_gemm_kernel(const float* __restri
   }
 }
 
+__global__ __launch_bounds__(256, 2) void corr_gemm_kernel(const float* __restrict__ Z, int n, int L_pad,
+                                                           int nb, int tiles, int tiles_per_xcd,
+                                                           float* __restrict__ W) {
+  // Blocks are handed to the 8 XCDs round-robin; give each XCD a contiguous run of tiles
+  // (tiles in one block-row share their A operand, which then stays in that XCD's L2).
+  const int xcd = blockIdx.x & 7;
+  const int t = xcd * tiles_per_xcd + (blockIdx.x >> 3);
+  if (t >= tiles) return;
+  int bi, bj;
+  upper_tri_coords(t, nb, bi, bj);
+  __shared__ __attribute__((aligned(16))) float smem[kGemmSmem];
+  gemm_tile(Z, n, L_pad, W, bi, bj, smem);
+}
+
+// Batched forms: one launch over every instance's rows / tiles.
+__global__ __launch_bounds__(256) void batch_standardize_kernel(const BatchJob* __restrict__ jobs,
+                                                                const int* __restrict__ list,
+                                                                const int* __restrict__ prefix, int nlist,
+                                                                int total) {
+  const int unit = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (unit >= total) return;
+  const int i = find_unit(prefix, nlist, unit);
+  const BatchJob& J = jobs[list[i]];
+  standardize_row(J.X, J.n, J.L, J.Z, J.L_pad, J.flags, unit - prefix[i], threadIdx.x & 63);
+}
+
+__global__ __launch_bounds__(256, 2) void batch_gemm_kernel(const BatchJob* __restrict__ jobs,
+                                                            const int* __restrict__ list,
+                                                            const int* __restrict__ prefix, int nlist,
+                                                            int total, int per_xcd) {
+  const int xcd = blockIdx.x & 7;
+  const int t = xcd * per_xcd + (blockIdx.x >> 3);
+  if (t >= total) return;
+  const int i = find_unit(prefix, nlist, t);
+  const BatchJob& J = jobs[list[i]];
+  const int nb = (J.n + BM - 1) / BM;
+  int bi, bj;
+  upper_tri_coords(t - prefix[i], nb, bi, bj);
+  __shared__ __attribute__((aligned(16))) float smem[kGemmSmem];
+  gemm_tile(J.Z, J.n, J.L_pad, J.Wdst, bi, bj, smem);
+}
+
 hipError_t launch_standardize(const float* X, int n, int L, float* Z, int n_pad, int L_pad, uint32_t* flags,
                               hipStream_t s) {
   dim3 grid((n_pad + 3) / 4);
@@ -197,6 +234,27 @@ hipError_t launch_corr_gemm(const float* Z, int n, int L_pad, float* W, hipStrea
   return hipGetLastError();
 }
 
+hipError_t launch_batch_standardize(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                                    hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_standardize_kernel, dim3((total + 3) / 4), dim3(256), 0, s, jobs, list, prefix, nlist,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_gemm(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                             hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  const int per_xcd = (total + 7) / 8;
+  hipLaunchKernelGGL(batch_gemm_kernel, dim3(8 * per_xcd), dim3(256), 0, s, jobs, list, prefix, nlist, total,
+                     per_xcd);
+  return hipGetLastError();
+}
+
+int corr_tiles(int n) {
+  const int nb = (n + BM - 1) / BM;
+  return nb * (nb + 1) / 2;
+}
 int corr_row_pad() { return BM; }
 int corr_k_pad() { return BK; }
 

@@ -9,13 +9,10 @@
 
 namespace tmfg {
 
-// One thread per vertex v sums column v, which equals row v because W is bitwise
-// symmetric; adjacent threads read adjacent addresses, so each row of W is read once,
-// coalesced. Loads run a block ahead of the sequential float64 additions.
-__global__ __launch_bounds__(256) void seed_scores_kernel(const float* __restrict__ W, int n,
-                                                          double* __restrict__ scores) {
-  const int v = blockIdx.x * 256 + threadIdx.x;
-  if (v >= n) return;
+// One thread sums column v, which equals row v because W is bitwise symmetric; adjacent
+// threads read adjacent addresses, so each row of W is read once, coalesced. Loads run a
+// block ahead of the sequential float64 additions.
+__device__ void seed_column(const float* __restrict__ W, int n, double* __restrict__ scores, int v) {
   constexpr int U = 32;
   const float* col = W + v;
   double acc = 0.0;
@@ -41,6 +38,12 @@ __global__ __launch_bounds__(256) void seed_scores_kernel(const float* __restric
   }
   for (; u < n; ++u) acc += (u == v) ? 0.0 : (double)col[(size_t)u * n];
   scores[v] = acc;
+}
+
+__global__ __launch_bounds__(256) void seed_scores_kernel(const float* __restrict__ W, int n,
+                                                          double* __restrict__ scores) {
+  const int v = blockIdx.x * 256 + threadIdx.x;
+  if (v < n) seed_column(W, n, scores, v);
 }
 
 // Top-4 by (score desc, id asc), one 256-thread workgroup.
@@ -94,13 +97,9 @@ __global__ __launch_bounds__(256) void seed_top4_kernel(const double* __restrict
 }
 
 // Flags non-finite entries and entries whose mirror has different bits. Each 32x32 tile
-// (i0, j0) with i0 <= j0 is read directly and transposed through LDS.
-__global__ __launch_bounds__(256) void validate_kernel(const float* __restrict__ W, int n,
-                                                       uint32_t* __restrict__ flags) {
-  __shared__ uint32_t t[32][33];
-  const int nb = (n + 31) / 32;
-  int bi, bj;
-  upper_tri_coords(blockIdx.x, nb, bi, bj);
+// (bi, bj) with bi <= bj is read directly and transposed through LDS.
+__device__ void validate_tile(const float* __restrict__ W, int n, int bi, int bj, uint32_t* __restrict__ flags,
+                              uint32_t (*t)[33]) {
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   uint32_t bad = 0;
   for (int r = ty; r < 32; r += 8) {
@@ -125,6 +124,39 @@ __global__ __launch_bounds__(256) void validate_kernel(const float* __restrict__
   if (bad) atomicOr(flags, bad);
 }
 
+__global__ __launch_bounds__(256) void validate_kernel(const float* __restrict__ W, int n,
+                                                       uint32_t* __restrict__ flags) {
+  __shared__ uint32_t t[32][33];
+  int bi, bj;
+  upper_tri_coords(blockIdx.x, (n + 31) / 32, bi, bj);
+  validate_tile(W, n, bi, bj, flags, t);
+}
+
+// Batched forms.
+__global__ __launch_bounds__(256) void batch_seed_kernel(const BatchJob* __restrict__ jobs,
+                                                         const int* __restrict__ list,
+                                                         const int* __restrict__ prefix, int nlist, int total) {
+  const int unit = blockIdx.x * 256 + threadIdx.x;
+  if (unit >= total) return;
+  const int i = find_unit(prefix, nlist, unit);
+  const BatchJob& J = jobs[list[i]];
+  seed_column(J.W, J.n, J.scores, unit - prefix[i]);
+}
+
+__global__ __launch_bounds__(256) void batch_validate_kernel(const BatchJob* __restrict__ jobs,
+                                                             const int* __restrict__ list,
+                                                             const int* __restrict__ prefix, int nlist,
+                                                             int total) {
+  __shared__ uint32_t t[32][33];
+  const int unit = blockIdx.x;
+  if (unit >= total) return;
+  const int i = find_unit(prefix, nlist, unit);
+  const BatchJob& J = jobs[list[i]];
+  int bi, bj;
+  upper_tri_coords(unit - prefix[i], (J.n + 31) / 32, bi, bj);
+  validate_tile(J.W, J.n, bi, bj, J.flags, t);
+}
+
 hipError_t launch_seed_scores(const float* W, int n, double* scores, hipStream_t s) {
   hipLaunchKernelGGL(seed_scores_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, n, scores);
   return hipGetLastError();
@@ -136,9 +168,28 @@ hipError_t launch_seed_top4(const double* scores, int n, int32_t* seed4, hipStre
 }
 
 hipError_t launch_validate(const float* W, int n, uint32_t* flags, hipStream_t s) {
-  const int nb = (n + 31) / 32;
-  hipLaunchKernelGGL(validate_kernel, dim3(nb * (nb + 1) / 2), dim3(256), 0, s, W, n, flags);
+  hipLaunchKernelGGL(validate_kernel, dim3(validate_tiles(n)), dim3(256), 0, s, W, n, flags);
   return hipGetLastError();
+}
+
+hipError_t launch_batch_seed(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                             hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_seed_kernel, dim3((total + 255) / 256), dim3(256), 0, s, jobs, list, prefix, nlist,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_validate(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                                 hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_validate_kernel, dim3(total), dim3(256), 0, s, jobs, list, prefix, nlist, total);
+  return hipGetLastError();
+}
+
+int validate_tiles(int n) {
+  const int nb = (n + 31) / 32;
+  return nb * (nb + 1) / 2;
 }
 
 }  // namespace tmfg

@@ -59,16 +59,13 @@ __device__ void wave_bitonic(uint32_t* k, uint16_t* id, int sz, int lane) {
 }
 
 template <int BLOCK, int EPT>
-__global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restrict__ W, int n,
-                                                          uint16_t* __restrict__ idx, float* __restrict__ vals,
-                                                          int64_t ldi, int sub_log2) {
+__device__ void sort_row(const float* __restrict__ W, int n, uint16_t* __restrict__ idx, float* __restrict__ vals,
+                         int64_t ldi, int sub_log2, int v, uint8_t* smem) {
   constexpr int NWAVE = BLOCK / kWave;
-  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   __shared__ uint32_t red_lo[NWAVE], red_hi[NWAVE];
   __shared__ int nbig;
   __shared__ int big_list[kMaxBig];
 
-  const int v = blockIdx.x;
   const int m = n - 1;
   const int m_al = (m + 7) & ~7;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -249,14 +246,35 @@ __global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restric
   }
 }
 
-namespace {
-int sort_sub_log2(int n) {
+__host__ __device__ inline int sort_sub_log2(int n) {
   const int m = n - 1;
   const int S = m < kSamples ? m : kSamples;
   int s = 0;
   while (s < 5 && (int64_t)(S + 1) * (2 << s) * 2 <= m) ++s;
   return s;
 }
+
+template <int BLOCK, int EPT>
+__global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restrict__ W, int n,
+                                                          uint16_t* __restrict__ idx, float* __restrict__ vals,
+                                                          int64_t ldi, int sub_log2) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  sort_row<BLOCK, EPT>(W, n, idx, vals, ldi, sub_log2, blockIdx.x, smem);
+}
+
+template <int BLOCK, int EPT>
+__global__ __launch_bounds__(BLOCK) void batch_sort_kernel(const BatchJob* __restrict__ jobs,
+                                                           const int* __restrict__ list,
+                                                           const int* __restrict__ prefix, int nlist, int total) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  const int unit = blockIdx.x;
+  if (unit >= total) return;
+  const int i = find_unit(prefix, nlist, unit);
+  const BatchJob& J = jobs[list[i]];
+  sort_row<BLOCK, EPT>(J.W, J.n, J.idx, J.vals, J.ldi, sort_sub_log2(J.n), unit - prefix[i], smem);
+}
+
+namespace {
 size_t sort_lds_bytes(int n, int sub_log2) {
   const int m = n - 1;
   const int m_al = (m + 7) & ~7;
@@ -268,15 +286,73 @@ template <int BLOCK, int EPT>
 hipError_t launch_sort_t(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
   const int sl = sort_sub_log2(n);
   const size_t lds = sort_lds_bytes(n, sl);
-  auto k = sort_rows_kernel<BLOCK, EPT>;
-  hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k, dim3(n), dim3(BLOCK), lds, s, W, n, idx, vals, ldi, sl);
+  hipLaunchKernelGGL((sort_rows_kernel<BLOCK, EPT>), dim3(n), dim3(BLOCK), lds, s, W, n, idx, vals, ldi, sl);
   return hipGetLastError();
 }
 }  // namespace
 
 int64_t sort_row_stride(int n) { return round_up(n - 1 > 0 ? n - 1 : 1, 8); }
+
+template <int BLOCK, int EPT>
+hipError_t launch_batch_sort_t(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                               int n_max, hipStream_t s) {
+  const size_t lds = sort_lds_bytes(n_max, sort_sub_log2(n_max));
+  hipLaunchKernelGGL((batch_sort_kernel<BLOCK, EPT>), dim3(total), dim3(BLOCK), lds, s, jobs, list, prefix, nlist,
+                     total);
+  return hipGetLastError();
+}
+
+// Let every sort kernel use all of the LDS the static arrays leave free (set once).
+template <int BLOCK, int EPT>
+hipError_t sort_attr_t() {
+  const void* ks[2] = {(const void*)sort_rows_kernel<BLOCK, EPT>, (const void*)batch_sort_kernel<BLOCK, EPT>};
+  for (const void* k : ks) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, k);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t sort_init_attributes() {
+  hipError_t e;
+  if ((e = sort_attr_t<256, 1>()) != hipSuccess) return e;
+  if ((e = sort_attr_t<256, 4>()) != hipSuccess) return e;
+  if ((e = sort_attr_t<512, 4>()) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 4>()) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 8>()) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 12>()) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 16>()) != hipSuccess) return e;
+  return sort_attr_t<1024, 20>();
+}
+
+int sort_class(int n) {
+  if (n <= 256) return 0;
+  if (n <= 1024) return 1;
+  if (n <= 2048) return 2;
+  if (n <= 4096) return 3;
+  if (n <= 8192) return 4;
+  if (n <= 12288) return 5;
+  if (n <= 16384) return 6;
+  return 7;
+}
+
+hipError_t launch_batch_sort(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
+                             int n_max, hipStream_t s) {
+  if (total <= 0) return hipSuccess;
+  switch (sort_class(n_max)) {
+    case 0: return launch_batch_sort_t<256, 1>(jobs, list, prefix, nlist, total, n_max, s);
+    case 1: return launch_batch_sort_t<256, 4>(jobs, list, prefix, nlist, total, n_max, s);
+    case 2: return launch_batch_sort_t<512, 4>(jobs, list, prefix, nlist, total, n_max, s);
+    case 3: return launch_batch_sort_t<1024, 4>(jobs, list, prefix, nlist, total, n_max, s);
+    case 4: return launch_batch_sort_t<1024, 8>(jobs, list, prefix, nlist, total, n_max, s);
+    case 5: return launch_batch_sort_t<1024, 12>(jobs, list, prefix, nlist, total, n_max, s);
+    case 6: return launch_batch_sort_t<1024, 16>(jobs, list, prefix, nlist, total, n_max, s);
+    default: return launch_batch_sort_t<1024, 20>(jobs, list, prefix, nlist, total, n_max, s);
+  }
+}
 
 hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
   if (n <= 256) return launch_sort_t<256, 1>(W, n, idx, vals, ldi, s);
