@@ -32,8 +32,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--batch", type=int, default=512, help="instances in the c4 batch")
+    ap.add_argument("--requests", type=int, default=2200, help="c5: requests per replay (the first 200 warm up)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1500)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -241,6 +242,111 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def _percentile(v, p):
+    """Nearest-rank percentile."""
+    v = np.sort(np.asarray(v, dtype=np.float64))
+    return float(v[min(len(v) - 1, max(0, int(np.ceil(p / 100.0 * len(v))) - 1))])
+
+
+def _replay(srv, Xs, t_unit, qps, warm):
+    """Submit every request at its arrival time (all at once when qps is None) while a
+    second thread collects results in order; latencies of the requests after `warm`."""
+    import queue
+    import threading
+    q = queue.Queue()
+    out = [None] * len(Xs)
+
+    def collect():
+        for _ in range(len(Xs)):
+            i, t = q.get()
+            out[i] = srv.poll(t, wait_ms=-1)
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = srv.now_ns() + 20_000_000
+    for i, X in enumerate(Xs):
+        arrival = 0
+        if qps is not None:
+            arrival = t0 + int(t_unit[i] / qps * 1e9)
+            while True:
+                d = arrival - srv.now_ns()
+                if d <= 0:
+                    break
+                if d > 2_000_000:
+                    time.sleep((d - 1_000_000) * 1e-9)
+        q.put((i, srv.submit(X, arrival)))
+    th.join()
+    bad = [i for i, r in enumerate(out) if r["status"] != 0]
+    if bad:
+        raise RuntimeError(f"requests failed: {bad[:5]}")
+    meas = out[warm:]
+    lat = [(r["done_ns"] - r["arrival_ns"]) * 1e-6 for r in meas]
+    span = (max(r["done_ns"] for r in meas) - min(r["arrival_ns"] for r in meas)) * 1e-9
+    return {"p50_ms": round(_percentile(lat, 50), 2), "p99_ms": round(_percentile(lat, 99), 2),
+            "mean_ms": round(float(np.mean(lat)), 2), "builds_per_s": round(len(meas) / span, 1),
+            "requests": len(meas)}
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals of rolling-window requests (n log-uniform in [100, 8000],
+    L = 256) from host memory through the request server; p50/p99 latency (done - arrival,
+    queueing included) at 0.5x and 0.8x of the saturated rate, against serial plain builds
+    under the same arrival trace."""
+    import torch
+    import paper_2408_09399_amd as tm
+    from paper_2408_09399_amd import synth
+    warm = min(200, args.requests // 10)
+    trace = synth.serving_trace(1.0, args.requests)          # arrival times at 1 request/s
+    Xs = [r.series.X for r in trace]
+    t_unit = np.array([r.t_arrival for r in trace])
+    n_max = max(X.shape[0] for X in Xs)
+    srv = tm.Server(hbm_budget=96 << 30, host_budget=4 << 30, max_batch=512, n_streams=2,
+                    n_max=n_max, L_max=256)
+    _replay(srv, Xs[: warm], t_unit, None, 0)                # first use: code paths, caches
+    sat = _replay(srv, Xs, t_unit, None, 0)                  # everything at once
+    rates = {}
+    for f in (0.5, 0.8):
+        qps = f * sat["builds_per_s"]
+        r = _replay(srv, Xs, t_unit, qps, warm)
+        r["qps"] = round(qps, 1)
+        rates[f"{f}x"] = r
+    srv.close()
+
+    # serial plain builds of the same requests, one at a time in arrival order: service time
+    # = copy in + build + copy out; latency from the single-server queue at each rate
+    dev = torch.device("cuda:0")
+    plan = tm.Plan(n_max, 256)
+    service = np.empty(len(Xs))
+    for i, X in enumerate(Xs):
+        t0 = time.perf_counter()
+        res = tm.build(X=torch.from_numpy(X).to(dev), plan=plan)
+        res.to_numpy()
+        service[i] = time.perf_counter() - t0
+    plan.close()
+    serial = {}
+    for key, r in rates.items():
+        arr = t_unit / r["qps"]
+        done = np.empty(len(Xs))
+        free = 0.0
+        for i in range(len(Xs)):
+            free = max(free, arr[i]) + service[i]
+            done[i] = free
+        lat = (done - arr)[warm:] * 1e3
+        serial[key] = {"p50_ms": round(_percentile(lat, 50), 2), "p99_ms": round(_percentile(lat, 99), 2)}
+    out = {
+        "metric": "p50/p99 latency at fixed QPS (request server, continuous batching)",
+        "value": rates["0.5x"]["p99_ms"], "unit": "ms (p99 at 0.5x saturated QPS)", "n_gpus": 1,
+        "steps": len(Xs) - warm, "warmup": warm, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"Poisson arrivals of {len(Xs)} rolling-window requests, n log-uniform in "
+                               f"[100, 8000], L=256, from host memory", "requests": len(Xs),
+                   "server": {"max_batch": 512, "n_streams": 2}},
+        "saturated": sat, "at_rate": rates,
+        "serial_plain": {"builds_per_s": round(len(Xs) / float(service.sum()), 1), "at_rate": serial},
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -250,6 +356,8 @@ def main():
         calibration_copy()
     if args.config == "c4":
         return bench_batch(args)
+    if args.config == "c5":
+        return bench_serve(args)
     import torch
     import paper_2408_09399_amd as tm
 

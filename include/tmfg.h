@@ -58,7 +58,8 @@ typedef enum {
   TMFG_E_DEGENERATE = 5,  /* a series with all values equal: no Pearson correlation */
   TMFG_E_NOMEM = 6,       /* device allocation failed */
   TMFG_E_HIP = 7,         /* a HIP runtime call failed; see tmfg_last_hip_error() */
-  TMFG_E_INTERNAL = 8     /* an internal consistency check failed on the device */
+  TMFG_E_INTERNAL = 8,    /* an internal consistency check failed on the device */
+  TMFG_PENDING = 9        /* server: the request has not finished yet */
 } tmfg_status;
 
 /* Plan and batch flags. */
@@ -143,6 +144,77 @@ size_t tmfg_batch_footprint_bytes(const tmfg_job* jobs, int32_t count, uint32_t 
 /* One-call form: builds (or reuses, when the job array is the same as the previous call's)
    a batch kept by the plan, and runs it on `stream`. The plan's n_max does not limit it. */
 tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count, hipStream_t stream);
+
+/* ---- Serving: requests from host memory, continuous batching ---------------------- */
+/* A server owns one device region (hbm_budget bytes) and one pinned host region
+   (host_budget bytes), allocated at creation, and a scheduler thread. Requests wait in
+   arrival order; each is admitted when its device footprint (input, scratch, results) and
+   host footprint (staged input, results) fit in what is free. Whenever one of n_streams
+   stream slots is idle, every admitted request (up to max_batch) is dispatched there as
+   one grouped batch (the kernels of tmfg_batch_run, launched directly), so a new batch
+   starts while earlier ones still run. A request's results stay in the pinned region
+   until it is polled: requests that are never polled hold host memory and can stall
+   admission. Every request gets the result tmfg_build gives it, bit for bit.
+   submit, poll and stats may be called from any host thread. */
+typedef struct tmfg_server_s* tmfg_server;
+
+typedef struct {
+  size_t hbm_budget;      /* device bytes for requests in flight */
+  size_t host_budget;     /* pinned host bytes for staged inputs and unread results */
+  int32_t max_batch;      /* requests one dispatch groups, at most (1..4096) */
+  int32_t n_streams;      /* dispatches in flight at once (1..4) */
+  int32_t n_max;          /* largest n accepted (4..20480) */
+  int32_t L_max;          /* largest L accepted (>= 2) */
+} tmfg_server_config;
+
+/* Result of one request, filled by tmfg_server_poll. The array pointers are HOST buffers
+   given by the caller (sizes as in tmfg_job for this n), or NULL to skip that output. */
+typedef struct {
+  int32_t* order;
+  int32_t* edges;
+  int32_t* steps;
+  float* step_gain;
+  int32_t* faces;
+  int32_t n;              /* out */
+  int32_t status;         /* out: tmfg_status of the build */
+  int64_t arrival_ns;     /* out: server clock (tmfg_server_now_ns) */
+  int64_t dispatch_ns;    /* out: when its batch was enqueued */
+  int64_t done_ns;        /* out: when the scheduler saw its batch finish */
+} tmfg_server_result;
+
+typedef struct {
+  int64_t submitted, completed, dispatches, waiting;
+  double p50_ms, p99_ms, mean_ms, max_ms;   /* latency done - arrival, completed requests */
+  double builds_per_s;                      /* completed / (last done - first arrival) */
+  double mean_batch;                        /* requests per dispatch */
+} tmfg_server_report;
+
+/* Allocates both regions, creates the stream slots and starts the scheduler thread on the
+   current HIP device. */
+tmfg_status tmfg_server_create(tmfg_server* server, const tmfg_server_config* config);
+
+/* Queues one build of the n x L series at X_host (host memory, float32 row-major; copied
+   before the call returns). arrival_ns is the request's arrival on the server clock, or 0
+   for now. TMFG_E_SIZE if n or L is out of range or the request can never fit either
+   budget. *ticket identifies the request in tmfg_server_poll. */
+tmfg_status tmfg_server_submit(tmfg_server server, const float* X_host, int32_t n, int32_t L, int64_t arrival_ns,
+                               int64_t* ticket);
+
+/* Waits up to wait_ms milliseconds (negative: until done) for a request. Returns
+   TMFG_PENDING if it has not finished; otherwise copies its results into `result`,
+   returns TMFG_OK (the build's own status is result->status) and forgets the ticket.
+   TMFG_E_INVALID for an unknown or already collected ticket. */
+tmfg_status tmfg_server_poll(tmfg_server server, int64_t ticket, int32_t wait_ms, tmfg_server_result* result);
+
+/* Counters and latency percentiles since creation or the last reset. */
+tmfg_status tmfg_server_stats(tmfg_server server, tmfg_server_report* report, int32_t reset);
+
+/* Stops the scheduler after the batches in flight finish, and frees both regions. NULL is
+   a no-op. */
+tmfg_status tmfg_server_destroy(tmfg_server server);
+
+/* The server clock: monotonic nanoseconds. */
+int64_t tmfg_server_now_ns(void);
 
 /* ---- The stages of a build, callable on their own ------------------------------- */
 

@@ -4,9 +4,9 @@ The compute path is libtmfg.so (hand-written HIP for gfx950 behind the C ABI in
 include/tmfg.h); this package holds its ctypes binding and the seeded synthetic input
 generators. The library is loaded on first use, and a missing build raises.
 """
-from .binding import (Plan, Result, Batch, TmfgError, build, correlation, sort_rows, seed, face_sweep,
-                      footprint_bytes, alloc_result, STATUS, NO_VALIDATE, TIMING, BATCH_NO_GRAPH)
+from .binding import (Plan, Result, Batch, Server, TmfgError, build, correlation, sort_rows, seed, face_sweep,
+                      footprint_bytes, alloc_result, STATUS, NO_VALIDATE, TIMING, BATCH_NO_GRAPH, PENDING)
 
-__all__ = ["Plan", "Result", "Batch", "TmfgError", "build", "correlation", "sort_rows", "seed",
+__all__ = ["Plan", "Result", "Batch", "Server", "TmfgError", "build", "correlation", "sort_rows", "seed",
            "face_sweep", "footprint_bytes", "alloc_result", "STATUS", "NO_VALIDATE", "TIMING",
-           "BATCH_NO_GRAPH"]
+           "BATCH_NO_GRAPH", "PENDING"]

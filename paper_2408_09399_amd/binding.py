@@ -18,8 +18,9 @@ LIB_PATH = os.path.join(HERE, "libtmfg.so")
 STATUS = {
     0: "TMFG_OK", 1: "TMFG_E_INVALID", 2: "TMFG_E_SIZE", 3: "TMFG_E_NONFINITE",
     4: "TMFG_E_ASYMMETRIC", 5: "TMFG_E_DEGENERATE", 6: "TMFG_E_NOMEM", 7: "TMFG_E_HIP",
-    8: "TMFG_E_INTERNAL",
+    8: "TMFG_E_INTERNAL", 9: "TMFG_PENDING",
 }
+PENDING = 9
 NO_VALIDATE = 1 << 0
 TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
@@ -43,6 +44,12 @@ SIGNATURES = {
     "tmfg_batch_destroy": (_I, [_P]),
     "tmfg_batch_footprint_bytes": (ctypes.c_size_t, [_P, _I, ctypes.c_uint32]),
     "tmfg_build_batch": (_I, [_P, _P, _I, _P]),
+    "tmfg_server_create": (_I, [ctypes.POINTER(_P), _P]),
+    "tmfg_server_submit": (_I, [_P, _P, _I, _I, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
+    "tmfg_server_poll": (_I, [_P, ctypes.c_int64, _I, _P]),
+    "tmfg_server_stats": (_I, [_P, _P, _I]),
+    "tmfg_server_destroy": (_I, [_P]),
+    "tmfg_server_now_ns": (ctypes.c_int64, []),
     "tmfg_status_string": (ctypes.c_char_p, [_I]),
     "tmfg_last_hip_error": (ctypes.c_int, []),
 }
@@ -63,6 +70,24 @@ class Job(ctypes.Structure):
         ("n", _I), ("L", _I), ("X", _P), ("W", _P), ("W_out", _P), ("order", _P),
         ("edges", _P), ("steps", _P), ("step_gain", _P), ("faces", _P), ("status", _P),
     ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("host_budget", ctypes.c_size_t), ("max_batch", _I),
+                ("n_streams", _I), ("n_max", _I), ("L_max", _I)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("order", _P), ("edges", _P), ("steps", _P), ("step_gain", _P), ("faces", _P),
+                ("n", _I), ("status", _I), ("arrival_ns", ctypes.c_int64), ("dispatch_ns", ctypes.c_int64),
+                ("done_ns", ctypes.c_int64)]
+
+
+class ServerReport(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("dispatches", ctypes.c_int64),
+                ("waiting", ctypes.c_int64), ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double), ("builds_per_s", ctypes.c_double),
+                ("mean_batch", ctypes.c_double)]
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -322,6 +347,70 @@ class Batch:
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
             _check(_lib().tmfg_batch_destroy(self._h), "tmfg_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request server over host memory (tmfg_server_*): submit numpy series, poll results.
+
+    The scheduler runs in the library's own thread on the device current at creation.
+    """
+
+    def __init__(self, hbm_budget: int, host_budget: int, max_batch: int = 512, n_streams: int = 2,
+                 n_max: int = 8192, L_max: int = 1024):
+        cfg = ServerConfig(hbm_budget, host_budget, max_batch, n_streams, n_max, L_max)
+        h = ctypes.c_void_p()
+        self._sizes = {}
+        _check(_lib().tmfg_server_create(ctypes.byref(h), ctypes.cast(ctypes.pointer(cfg), ctypes.c_void_p)),
+               "tmfg_server_create")
+        self._h = h
+
+    @staticmethod
+    def now_ns() -> int:
+        return int(_lib().tmfg_server_now_ns())
+
+    def submit(self, X, arrival_ns: int = 0) -> int:
+        """Queue a build of the (n, L) float32 series X (host memory, copied at once)."""
+        import numpy as np
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        n, L = X.shape
+        t = ctypes.c_int64()
+        _check(_lib().tmfg_server_submit(self._h, X.ctypes.data, n, L, int(arrival_ns), ctypes.byref(t)),
+               "tmfg_server_submit")
+        self._sizes[t.value] = n
+        return t.value
+
+    def poll(self, ticket: int, wait_ms: int = -1):
+        """None while the request is pending; else its outputs, build status and times."""
+        import numpy as np
+        n = self._sizes[ticket]
+        out = {"order": np.empty(n, np.int32), "edges": np.empty((3 * n - 6, 2), np.int32),
+               "steps": np.empty((max(n - 4, 0), 4), np.int32), "step_gain": np.empty(max(n - 4, 0), np.float32),
+               "faces": np.empty((2 * n - 4, 3), np.int32)}
+        r = ServerResult(*(out[k].ctypes.data if out[k].size else None
+                           for k in ("order", "edges", "steps", "step_gain", "faces")))
+        code = _lib().tmfg_server_poll(self._h, int(ticket), int(wait_ms), ctypes.byref(r))
+        if code == PENDING:
+            return None
+        _check(code, "tmfg_server_poll")
+        del self._sizes[ticket]
+        out.update(n=r.n, status=r.status, arrival_ns=r.arrival_ns, dispatch_ns=r.dispatch_ns, done_ns=r.done_ns)
+        return out
+
+    def stats(self, reset: bool = False) -> dict:
+        rep = ServerReport()
+        _check(_lib().tmfg_server_stats(self._h, ctypes.byref(rep), int(reset)), "tmfg_server_stats")
+        return {k: getattr(rep, k) for k, _ in ServerReport._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _check(_lib().tmfg_server_destroy(self._h), "tmfg_server_destroy")
             self._h = None
 
     def __del__(self):

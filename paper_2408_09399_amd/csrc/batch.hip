@@ -10,6 +10,7 @@
 #include "../../include/tmfg.h"
 #include "common.h"
 #include "internal.h"
+#include "batchplan.h"
 
 #include <algorithm>
 #include <cstring>
@@ -43,17 +44,163 @@ hipError_t init_attributes_once() {
 
 }  // namespace tmfg
 
-namespace {
+namespace tmfg {
 
-struct List {
-  int nlist = 0, total = 0, n_max = 0;
-  const int* d_list = nullptr;
-  const int* d_prefix = nullptr;
-};
+tmfg_status job_scratch_bytes(const tmfg_job& j, size_t* bytes) {
+  if ((j.X == nullptr) == (j.W == nullptr)) return TMFG_E_INVALID;
+  if (!j.order || !j.edges || !j.faces || !j.status) return TMFG_E_INVALID;
+  if (j.n < kMinN || j.n > kMaxN) return TMFG_E_SIZE;
+  if (j.n > 4 && (!j.steps || !j.step_gain)) return TMFG_E_INVALID;
+  if (j.X && j.L < 2) return TMFG_E_SIZE;
+  const int n = j.n;
+  const int64_t ldi = sort_row_stride(n);
+  size_t b = align256(sizeof(uint32_t)) + align256((size_t)n * ldi * 2) + align256((size_t)n * ldi * 4) +
+             align256((size_t)n * 8) + align256((size_t)(2 * n - 4) * 16);
+  if (j.X) {
+    const int n_pad = (int)round_up(n, corr_row_pad());
+    const int L_pad = (int)round_up(j.L, corr_k_pad());
+    b += align256((size_t)n_pad * L_pad * 4);
+    if (!j.W_out) b += align256((size_t)n * n * 4);
+  }
+  *bytes = b;
+  return TMFG_OK;
+}
 
-size_t al(size_t b) { return (b + 255) / 256 * 256; }
+size_t batch_ints_capacity(int count) { return (size_t)10 * count + 12 + 24 * 64; }
 
-}  // namespace
+tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, BatchSpec& spec) {
+  spec = BatchSpec();
+  spec.count = count;
+  spec.scratch.resize(count);
+  for (int i = 0; i < count; ++i) {
+    const tmfg_status st = job_scratch_bytes(jobs[i], &spec.scratch[i]);
+    if (st != TMFG_OK) return st;
+  }
+  std::vector<int> lx, lw, la(count), pre_rows{0}, pre_tiles{0}, pre_vt{0}, pre_cols{0};
+  std::vector<int> lsort[8], pre_sort[8];
+  int nmax_sort[8] = {0};
+  for (int c = 0; c < 8; ++c) pre_sort[c].push_back(0);
+  std::iota(la.begin(), la.end(), 0);
+  for (int i = 0; i < count; ++i) {
+    const tmfg_job& j = jobs[i];
+    pre_cols.push_back(pre_cols.back() + j.n);
+    if (j.X) {
+      lx.push_back(i);
+      pre_rows.push_back(pre_rows.back() + (int)round_up(j.n, corr_row_pad()));
+      pre_tiles.push_back(pre_tiles.back() + corr_tiles(j.n));
+    } else if (!(flags & TMFG_NO_VALIDATE)) {
+      lw.push_back(i);
+      pre_vt.push_back(pre_vt.back() + validate_tiles(j.n));
+    }
+    const int c = sort_class(j.n);
+    lsort[c].push_back(i);
+    pre_sort[c].push_back(pre_sort[c].back() + j.n);
+    nmax_sort[c] = std::max(nmax_sort[c], j.n);
+    spec.n_max = std::max(spec.n_max, j.n);
+  }
+  std::vector<int> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return jobs[x].n > jobs[y].n; });
+
+  std::vector<int>& ints = spec.ints;
+  auto put = [&](const std::vector<int>& v) {
+    const size_t off = ints.size();
+    ints.insert(ints.end(), v.begin(), v.end());
+    while (ints.size() % 64) ints.push_back(0);
+    return off;
+  };
+  auto list = [&](const std::vector<int>& l, const std::vector<int>& pre, int nmax) {
+    GroupList g;
+    g.nlist = (int)l.size();
+    g.total = pre.back();
+    g.n_max = nmax;
+    g.o_list = put(l);
+    g.o_prefix = put(pre);
+    return g;
+  };
+  spec.stdz = list(lx, pre_rows, 0);
+  spec.gemm = list(lx, pre_tiles, 0);
+  spec.valid = list(lw, pre_vt, 0);
+  spec.seed = list(la, pre_cols, 0);
+  for (int c = 0; c < 8; ++c) spec.sort[c] = list(lsort[c], pre_sort[c], nmax_sort[c]);
+  spec.o_order = put(order);
+  return TMFG_OK;
+}
+
+void batch_job_desc(const tmfg_job& j, char* scratch, BatchJob& J) {
+  char* cur = scratch;
+  auto take = [&](size_t bytes) {
+    char* p = cur;
+    cur += align256(bytes);
+    return p;
+  };
+  std::memset(&J, 0, sizeof(J));
+  J.n = j.n;
+  J.L = j.X ? j.L : 0;
+  J.ldi = sort_row_stride(j.n);
+  J.flags = (uint32_t*)take(4);
+  J.idx = (uint16_t*)take((size_t)j.n * J.ldi * 2);
+  J.vals = (float*)take((size_t)j.n * J.ldi * 4);
+  J.scores = (double*)take((size_t)j.n * 8);
+  J.frec = (uint4*)take((size_t)(2 * j.n - 4) * 16);
+  if (j.X) {
+    J.n_pad = (int)round_up(j.n, corr_row_pad());
+    J.L_pad = (int)round_up(j.L, corr_k_pad());
+    J.X = j.X;
+    J.Z = (float*)take((size_t)J.n_pad * J.L_pad * 4);
+    J.Wdst = j.W_out ? j.W_out : (float*)take((size_t)j.n * j.n * 4);
+    J.W = J.Wdst;
+  } else {
+    J.W = j.W;
+  }
+  J.order = j.order;
+  J.edges = j.edges;
+  J.steps = j.steps;
+  J.step_gain = j.step_gain;
+  J.faces = j.faces;
+  J.status = j.status;
+}
+
+hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_t s) {
+  const int* I = L.d_ints;
+  auto lp = [&](const GroupList& g) { return I + g.o_list; };
+  auto pp = [&](const GroupList& g) { return I + g.o_prefix; };
+  hipError_t e;
+  if ((e = launch_batch_reset(L.d_jobs, spec.count, L.d_queue, s)) != hipSuccess) return e;
+  if ((e = launch_batch_standardize(L.d_jobs, lp(spec.stdz), pp(spec.stdz), spec.stdz.nlist, spec.stdz.total, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_batch_gemm(L.d_jobs, lp(spec.gemm), pp(spec.gemm), spec.gemm.nlist, spec.gemm.total, s)) !=
+      hipSuccess)
+    return e;
+  if ((e = launch_batch_validate(L.d_jobs, lp(spec.valid), pp(spec.valid), spec.valid.nlist, spec.valid.total, s)) !=
+      hipSuccess)
+    return e;
+  for (size_t i = 0; i < L.w_copies.size(); ++i)
+    if ((e = hipMemcpyAsync(L.w_copies[i].second, L.w_copies[i].first, L.w_copy_bytes[i], hipMemcpyDeviceToDevice,
+                            s)) != hipSuccess)
+      return e;
+  if ((e = launch_batch_seed(L.d_jobs, lp(spec.seed), pp(spec.seed), spec.seed.nlist, spec.seed.total, s)) !=
+      hipSuccess)
+    return e;
+  for (int c = 0; c < 8; ++c) {
+    const GroupList& g = spec.sort[c];
+    if (g.nlist == 0) continue;
+    if ((e = launch_batch_sort(L.d_jobs, lp(g), pp(g), g.nlist, g.total, g.n_max, s)) != hipSuccess) return e;
+  }
+  return launch_batch_loop(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, nullptr, s);
+}
+
+hipError_t batch_grid(int device, int count, int n_max, int* grid) {
+  int cus = 0, per_cu = 0;
+  hipError_t e;
+  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess) return e;
+  if ((e = batch_loop_occupancy(&per_cu, n_max)) != hipSuccess) return e;
+  *grid = std::max(1, std::min(count, cus * std::max(per_cu, 1)));
+  return hipSuccess;
+}
+
+}  // namespace tmfg
 
 struct tmfg_batch_s {
   int device = 0;
@@ -61,14 +208,8 @@ struct tmfg_batch_s {
   uint32_t flags = 0;
   void* arena = nullptr;
   size_t arena_bytes = 0;
-  tmfg::BatchJob* d_jobs = nullptr;
-  int* d_queue = nullptr;
-  const int* d_order = nullptr;
-  int n_max = 0;
-  int grid = 0;
-  List stdz, gemm, valid, seed, sort[8];
-  std::vector<std::pair<const float*, float*>> w_copies;   // caller W -> W_out
-  std::vector<size_t> w_copy_bytes;
+  tmfg::BatchSpec spec;
+  tmfg::BatchLaunch launch;
   hipStream_t capture_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -76,34 +217,6 @@ struct tmfg_batch_s {
 };
 
 namespace {
-
-hipError_t enqueue(tmfg_batch b, hipStream_t s) {
-  hipError_t e;
-  if ((e = tmfg::launch_batch_reset(b->d_jobs, b->count, b->d_queue, s)) != hipSuccess) return e;
-  if ((e = tmfg::launch_batch_standardize(b->d_jobs, b->stdz.d_list, b->stdz.d_prefix, b->stdz.nlist,
-                                          b->stdz.total, s)) != hipSuccess)
-    return e;
-  if ((e = tmfg::launch_batch_gemm(b->d_jobs, b->gemm.d_list, b->gemm.d_prefix, b->gemm.nlist, b->gemm.total, s)) !=
-      hipSuccess)
-    return e;
-  if ((e = tmfg::launch_batch_validate(b->d_jobs, b->valid.d_list, b->valid.d_prefix, b->valid.nlist,
-                                       b->valid.total, s)) != hipSuccess)
-    return e;
-  for (size_t i = 0; i < b->w_copies.size(); ++i)
-    if ((e = hipMemcpyAsync(b->w_copies[i].second, b->w_copies[i].first, b->w_copy_bytes[i],
-                            hipMemcpyDeviceToDevice, s)) != hipSuccess)
-      return e;
-  if ((e = tmfg::launch_batch_seed(b->d_jobs, b->seed.d_list, b->seed.d_prefix, b->seed.nlist, b->seed.total, s)) !=
-      hipSuccess)
-    return e;
-  for (int c = 0; c < 8; ++c) {
-    const List& L = b->sort[c];
-    if (L.nlist == 0) continue;
-    if ((e = tmfg::launch_batch_sort(b->d_jobs, L.d_list, L.d_prefix, L.nlist, L.total, L.n_max, s)) != hipSuccess)
-      return e;
-  }
-  return tmfg::launch_batch_loop(b->d_jobs, b->d_order, b->count, b->d_queue, b->grid, b->n_max, nullptr, s);
-}
 
 void batch_free(tmfg_batch b) {
   if (!b) return;
@@ -119,27 +232,6 @@ tmfg_status fail(hipError_t e) {
   return e == hipErrorOutOfMemory ? TMFG_E_NOMEM : TMFG_E_HIP;
 }
 
-// Bytes of scratch one instance needs, and the check of its arguments.
-tmfg_status job_scratch(const tmfg_job& j, size_t* bytes) {
-  if ((j.X == nullptr) == (j.W == nullptr)) return TMFG_E_INVALID;
-  if (!j.order || !j.edges || !j.faces || !j.status) return TMFG_E_INVALID;
-  if (j.n < tmfg::kMinN || j.n > tmfg::kMaxN) return TMFG_E_SIZE;
-  if (j.n > 4 && (!j.steps || !j.step_gain)) return TMFG_E_INVALID;
-  if (j.X && j.L < 2) return TMFG_E_SIZE;
-  const int n = j.n;
-  const int64_t ldi = tmfg::sort_row_stride(n);
-  size_t b = al(sizeof(uint32_t)) + al((size_t)n * ldi * 2) + al((size_t)n * ldi * 4) + al((size_t)n * 8) +
-             al((size_t)(2 * n - 4) * 16);
-  if (j.X) {
-    const int n_pad = (int)tmfg::round_up(n, tmfg::corr_row_pad());
-    const int L_pad = (int)tmfg::round_up(j.L, tmfg::corr_k_pad());
-    b += al((size_t)n_pad * L_pad * 4);
-    if (!j.W_out) b += al((size_t)n * n * 4);
-  }
-  *bytes = b;
-  return TMFG_OK;
-}
-
 }  // namespace
 
 extern "C" {
@@ -147,10 +239,11 @@ extern "C" {
 size_t tmfg_batch_footprint_bytes(const tmfg_job* jobs, int32_t count, uint32_t flags) {
   (void)flags;
   if (!jobs || count <= 0) return 0;
-  size_t total = al((size_t)count * sizeof(tmfg::BatchJob)) + al(4) + al((size_t)(12 * count + 64) * 4);
+  size_t total = tmfg::align256((size_t)count * sizeof(tmfg::BatchJob)) + tmfg::align256(4) +
+                 tmfg::align256(tmfg::batch_ints_capacity(count) * 4);
   for (int i = 0; i < count; ++i) {
     size_t b = 0;
-    if (job_scratch(jobs[i], &b) != TMFG_OK) return 0;
+    if (tmfg::job_scratch_bytes(jobs[i], &b) != TMFG_OK) return 0;
     total += b;
   }
   return total;
@@ -161,11 +254,9 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
   *out = nullptr;
   if (!jobs || count <= 0) return TMFG_E_INVALID;
   if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_BATCH_NO_GRAPH)) return TMFG_E_INVALID;
-  std::vector<size_t> scratch(count);
-  for (int i = 0; i < count; ++i) {
-    const tmfg_status st = job_scratch(jobs[i], &scratch[i]);
-    if (st != TMFG_OK) return st;
-  }
+  tmfg::BatchSpec spec;
+  const tmfg_status st = tmfg::batch_describe(jobs, count, flags, spec);
+  if (st != TMFG_OK) return st;
   hipError_t e = tmfg::init_attributes_once();
   if (e != hipSuccess) return fail(e);
   tmfg_batch b = new (std::nothrow) tmfg_batch_s();
@@ -173,135 +264,44 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
   b->count = count;
   b->flags = flags;
   b->jobs.assign(jobs, jobs + count);
+  b->spec = std::move(spec);
   if ((e = hipGetDevice(&b->device)) != hipSuccess) {
     batch_free(b);
     return fail(e);
   }
 
-  // Work lists of every phase (host side first).
-  std::vector<int> lx, lw, la(count), pre_rows{0}, pre_tiles{0}, pre_vt{0}, pre_cols{0};
-  std::vector<int> lsort[8], pre_sort[8];
-  int nmax_sort[8] = {0};
-  for (int c = 0; c < 8; ++c) pre_sort[c].push_back(0);
-  std::iota(la.begin(), la.end(), 0);
-  for (int i = 0; i < count; ++i) {
-    const tmfg_job& j = jobs[i];
-    pre_cols.push_back(pre_cols.back() + j.n);
-    if (j.X) {
-      lx.push_back(i);
-      pre_rows.push_back(pre_rows.back() + (int)tmfg::round_up(j.n, tmfg::corr_row_pad()));
-      pre_tiles.push_back(pre_tiles.back() + tmfg::corr_tiles(j.n));
-    } else if (!(flags & TMFG_NO_VALIDATE)) {
-      lw.push_back(i);
-      pre_vt.push_back(pre_vt.back() + tmfg::validate_tiles(j.n));
-    }
-    const int c = tmfg::sort_class(j.n);
-    lsort[c].push_back(i);
-    pre_sort[c].push_back(pre_sort[c].back() + j.n);
-    nmax_sort[c] = std::max(nmax_sort[c], j.n);
-    b->n_max = std::max(b->n_max, j.n);
-  }
-  std::vector<int> order(count);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return jobs[x].n > jobs[y].n; });
-
   // One arena: job descriptors, the integer lists, the queue counter, per-job scratch.
-  std::vector<int> ints;
-  auto put = [&](const std::vector<int>& v) {
-    const size_t off = ints.size();
-    ints.insert(ints.end(), v.begin(), v.end());
-    while (ints.size() % 64) ints.push_back(0);
-    return off;
-  };
-  const size_t o_lx = put(lx), o_prow = put(pre_rows), o_ptile = put(pre_tiles), o_lw = put(lw), o_pvt = put(pre_vt),
-               o_la = put(la), o_pcol = put(pre_cols), o_order = put(order);
-  size_t o_ls[8], o_ps[8];
-  for (int c = 0; c < 8; ++c) {
-    o_ls[c] = put(lsort[c]);
-    o_ps[c] = put(pre_sort[c]);
-  }
-  const size_t jobs_bytes = al((size_t)count * sizeof(tmfg::BatchJob));
-  const size_t ints_bytes = al(ints.size() * 4);
-  size_t total = jobs_bytes + ints_bytes + al(4);
-  for (size_t x : scratch) total += x;
+  const size_t jobs_bytes = tmfg::align256((size_t)count * sizeof(tmfg::BatchJob));
+  const size_t ints_bytes = tmfg::align256(b->spec.ints.size() * 4);
+  size_t total = jobs_bytes + ints_bytes + tmfg::align256(4);
+  for (size_t x : b->spec.scratch) total += x;
   if ((e = hipMalloc(&b->arena, total)) != hipSuccess) {
     batch_free(b);
     return fail(e);
   }
   b->arena_bytes = total;
   char* base = (char*)b->arena;
-  b->d_jobs = (tmfg::BatchJob*)base;
+  tmfg::BatchLaunch& L = b->launch;
+  L.d_jobs = (tmfg::BatchJob*)base;
   int* d_ints = (int*)(base + jobs_bytes);
-  b->d_queue = (int*)(base + jobs_bytes + ints_bytes);
-  char* cur = base + jobs_bytes + ints_bytes + al(4);
-  auto take = [&](size_t bytes) {
-    char* p = cur;
-    cur += al(bytes);
-    return p;
-  };
+  L.d_ints = d_ints;
+  L.d_queue = (int*)(base + jobs_bytes + ints_bytes);
+  char* cur = base + jobs_bytes + ints_bytes + tmfg::align256(4);
   std::vector<tmfg::BatchJob> hj(count);
   for (int i = 0; i < count; ++i) {
-    const tmfg_job& j = jobs[i];
-    tmfg::BatchJob& J = hj[i];
-    std::memset(&J, 0, sizeof(J));
-    J.n = j.n;
-    J.L = j.X ? j.L : 0;
-    J.ldi = tmfg::sort_row_stride(j.n);
-    J.flags = (uint32_t*)take(4);
-    J.idx = (uint16_t*)take((size_t)j.n * J.ldi * 2);
-    J.vals = (float*)take((size_t)j.n * J.ldi * 4);
-    J.scores = (double*)take((size_t)j.n * 8);
-    J.frec = (uint4*)take((size_t)(2 * j.n - 4) * 16);
-    if (j.X) {
-      J.n_pad = (int)tmfg::round_up(j.n, tmfg::corr_row_pad());
-      J.L_pad = (int)tmfg::round_up(j.L, tmfg::corr_k_pad());
-      J.X = j.X;
-      J.Z = (float*)take((size_t)J.n_pad * J.L_pad * 4);
-      J.Wdst = j.W_out ? j.W_out : (float*)take((size_t)j.n * j.n * 4);
-      J.W = J.Wdst;
-    } else {
-      J.W = j.W;
-      if (j.W_out) {
-        b->w_copies.push_back({j.W, j.W_out});
-        b->w_copy_bytes.push_back((size_t)j.n * j.n * 4);
-      }
+    tmfg::batch_job_desc(jobs[i], cur, hj[i]);
+    cur += b->spec.scratch[i];
+    if (jobs[i].W && jobs[i].W_out) {
+      L.w_copies.push_back({jobs[i].W, jobs[i].W_out});
+      L.w_copy_bytes.push_back((size_t)jobs[i].n * jobs[i].n * 4);
     }
-    J.order = j.order;
-    J.edges = j.edges;
-    J.steps = j.steps;
-    J.step_gain = j.step_gain;
-    J.faces = j.faces;
-    J.status = j.status;
   }
-  if ((e = hipMemcpy(b->d_jobs, hj.data(), sizeof(tmfg::BatchJob) * count, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = hipMemcpy(d_ints, ints.data(), ints.size() * 4, hipMemcpyHostToDevice)) != hipSuccess) {
+  if ((e = hipMemcpy(L.d_jobs, hj.data(), sizeof(tmfg::BatchJob) * count, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = hipMemcpy(d_ints, b->spec.ints.data(), b->spec.ints.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
+      (e = tmfg::batch_grid(b->device, count, b->spec.n_max, &L.grid)) != hipSuccess) {
     batch_free(b);
     return fail(e);
   }
-  auto list = [&](size_t ol, size_t op, int nlist, int tot, int nmax) {
-    List L;
-    L.nlist = nlist;
-    L.total = tot;
-    L.n_max = nmax;
-    L.d_list = d_ints + ol;
-    L.d_prefix = d_ints + op;
-    return L;
-  };
-  b->stdz = list(o_lx, o_prow, (int)lx.size(), pre_rows.back(), 0);
-  b->gemm = list(o_lx, o_ptile, (int)lx.size(), pre_tiles.back(), 0);
-  b->valid = list(o_lw, o_pvt, (int)lw.size(), pre_vt.back(), 0);
-  b->seed = list(o_la, o_pcol, count, pre_cols.back(), 0);
-  for (int c = 0; c < 8; ++c) b->sort[c] = list(o_ls[c], o_ps[c], (int)lsort[c].size(), pre_sort[c].back(), nmax_sort[c]);
-  b->d_order = d_ints + o_order;
-
-  // Persistent loop grid: the workgroups that fit on the device at once, at most one per job.
-  int cus = 0, per_cu = 0;
-  if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device)) != hipSuccess ||
-      (e = tmfg::batch_loop_occupancy(&per_cu, b->n_max)) != hipSuccess) {
-    batch_free(b);
-    return fail(e);
-  }
-  b->grid = std::max(1, std::min(count, cus * std::max(per_cu, 1)));
 
   if (!(flags & TMFG_BATCH_NO_GRAPH)) {
     if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
@@ -309,7 +309,7 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
       batch_free(b);
       return fail(e);
     }
-    const hipError_t ee = enqueue(b, b->capture_stream);
+    const hipError_t ee = tmfg::batch_enqueue(b->spec, L, b->capture_stream);
     e = hipStreamEndCapture(b->capture_stream, &b->graph);
     if (ee != hipSuccess || e != hipSuccess) {
       batch_free(b);
@@ -326,7 +326,7 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
 
 tmfg_status tmfg_batch_run(tmfg_batch batch, hipStream_t stream) {
   if (!batch) return TMFG_E_INVALID;
-  hipError_t e = batch->exec ? hipGraphLaunch(batch->exec, stream) : enqueue(batch, stream);
+  hipError_t e = batch->exec ? hipGraphLaunch(batch->exec, stream) : tmfg::batch_enqueue(batch->spec, batch->launch, stream);
   if (e != hipSuccess) return fail(e);
   return TMFG_OK;
 }

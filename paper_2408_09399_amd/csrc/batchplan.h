@@ -1,0 +1,58 @@
+// Host-side description of one set of grouped launches over many independent builds
+// (internal to libtmfg). Used by the captured batches and by the request server.
+#pragma once
+#include "../../include/tmfg.h"
+#include "internal.h"
+
+#include <utility>
+#include <vector>
+
+namespace tmfg {
+
+inline size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// One phase's work list inside BatchSpec::ints: job indices at o_list, unit prefixes at
+// o_prefix (nlist + 1 entries, the last one is `total`).
+struct GroupList {
+  int nlist = 0, total = 0, n_max = 0;
+  size_t o_list = 0, o_prefix = 0;
+};
+
+struct BatchSpec {
+  int count = 0, n_max = 0;
+  std::vector<int> ints;             // every list, each padded to a multiple of 64 ints
+  GroupList stdz, gemm, valid, seed, sort[8];
+  size_t o_order = 0;                // job indices by n descending: the loop's queue order
+  std::vector<size_t> scratch;       // device scratch bytes of each job
+};
+
+// Checks one job's arguments and gives the scratch bytes it needs in a batch.
+tmfg_status job_scratch_bytes(const tmfg_job& j, size_t* bytes);
+
+// Work lists and scratch sizes of a set of jobs.
+tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, BatchSpec& spec);
+
+// Ints the lists of a batch of `count` jobs can take at most.
+size_t batch_ints_capacity(int count);
+
+// Device descriptor of a job whose scratch (job_scratch_bytes) starts at `scratch`.
+void batch_job_desc(const tmfg_job& j, char* scratch, BatchJob& J);
+
+// Where the descriptors and lists of one launch set live on the device.
+struct BatchLaunch {
+  BatchJob* d_jobs = nullptr;
+  const int* d_ints = nullptr;
+  int* d_queue = nullptr;
+  int grid = 1;                                             // persistent loop workgroups
+  std::vector<std::pair<const float*, float*>> w_copies;    // caller W -> W_out
+  std::vector<size_t> w_copy_bytes;
+};
+
+// Enqueues every phase of the batch on `s` (no allocation, no synchronisation).
+hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_t s);
+
+// Persistent loop grid for `count` jobs of largest size n_max: the loop workgroups that
+// fit on the device at once, at most one per job.
+hipError_t batch_grid(int device, int count, int n_max, int* grid);
+
+}  // namespace tmfg

@@ -132,6 +132,7 @@ const char* tmfg_status_string(tmfg_status s) {
     case TMFG_E_NOMEM: return "out of device memory";
     case TMFG_E_HIP: return "HIP runtime error";
     case TMFG_E_INTERNAL: return "internal error";
+    case TMFG_PENDING: return "request pending";
   }
   return "unknown status";
 }

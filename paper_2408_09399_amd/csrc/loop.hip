@@ -27,8 +27,8 @@
 // Best vertex of a face: the threshold walk over the three corners' sorted rows (the
 // per-vertex sort of Algorithm 1, with the similarity of every entry stored beside its id).
 // Each round takes the first kCand uninserted entries at or after each list's position and
-// evaluates them; a vertex found in several of the three lists is evaluated once, with the
-// similarities those lists carry, and only the missing ones are read from W. Any vertex
+// evaluates each with the similarity its list carries and the other two read from W (a
+// vertex found in several lists is evaluated once per list, to the same gain). Any vertex
 // not yet evaluated has W[x][u] <= the value of the bound entry of x's list (the next
 // uninserted entry, or the last position scanned) for x = a, b, c, so its gain is at most
 // T = (A + B) + C of those values (float32 addition is monotone). The walk stops when the

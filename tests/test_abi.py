@@ -31,8 +31,9 @@ def test_library_exports_every_symbol():
 
 def test_status_strings():
     lib = binding.lib()
-    for code in range(9):
-        assert lib.tmfg_status_string(code)
+    for code in range(10):
+        assert b"unknown" not in lib.tmfg_status_string(code)
+    assert b"unknown" in lib.tmfg_status_string(10)
 
 
 def test_host_side_argument_errors():
@@ -58,3 +59,26 @@ def test_footprint_grows_quadratically():
     f2 = binding.footprint_bytes(10000, 512)
     assert 3.5 < f2 / f1 < 4.5
     assert binding.footprint_bytes(3, 10) == 0
+
+
+def test_server_host_side_argument_errors():
+    lib = binding.lib()
+    h = ctypes.c_void_p()
+    cfg = binding.ServerConfig(1 << 20, 1 << 20, 16, 2, 100, 64)
+    pc = ctypes.cast(ctypes.pointer(cfg), ctypes.c_void_p)
+    assert lib.tmfg_server_create(None, pc) == 1
+    assert lib.tmfg_server_create(ctypes.byref(h), None) == 1
+    for field, bad, code in [("hbm_budget", 0, 1), ("host_budget", 0, 1), ("max_batch", 0, 1),
+                             ("max_batch", 4097, 1), ("n_streams", 0, 1), ("n_streams", 5, 1),
+                             ("n_max", 3, 2), ("n_max", 20481, 2), ("L_max", 1, 2)]:
+        c = binding.ServerConfig(1 << 20, 1 << 20, 16, 2, 100, 64)
+        setattr(c, field, bad)
+        assert lib.tmfg_server_create(ctypes.byref(h), ctypes.cast(ctypes.pointer(c), ctypes.c_void_p)) == code, field
+    t = ctypes.c_int64()
+    assert lib.tmfg_server_submit(None, None, 10, 10, 0, ctypes.byref(t)) == 1
+    assert lib.tmfg_server_poll(None, 1, 0, None) == 1
+    assert lib.tmfg_server_stats(None, None, 0) == 1
+    assert lib.tmfg_server_destroy(None) == 0
+    a = lib.tmfg_server_now_ns()
+    b = lib.tmfg_server_now_ns()
+    assert 0 < a <= b
