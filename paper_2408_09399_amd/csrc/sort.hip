@@ -4,365 +4,344 @@
 // Order: W[v][u] descending, then u ascending; v itself is left out, so each row yields
 // n-1 ids (16-bit). -0.0 and +0.0 compare equal.
 //
-// One workgroup sorts one row entirely in LDS:
-//  1. the row is read once (coalesced) into registers as 32-bit keys k = ~ord(W[v][u]),
-//     for which "larger similarity" is "smaller key";
-//  2. 256 evenly spaced samples of the row are ranked against each other (rank by
-//     counting) and become splitters; every element finds its splitter interval by binary
-//     search and a linear sub-bucket inside it. The bucket index is a non-decreasing
-//     function of the key, so buckets come out in key order and are about equally full
-//     whatever the value distribution (Pearson rows crowd near 1);
-//  3. a histogram, a scan and a scatter (LDS atomics) place each element in its bucket;
-//     order inside a bucket is arbitrary at this point;
-//  4. inside a bucket of at most kRankMax elements each element counts the elements that
-//     precede it by (key, id), which is its exact position: the composite key is unique,
-//     so the outcome is deterministic even though the scatter is not;
-//  5. larger buckets (many exactly equal similarities) are bitonic-sorted by one wave each;
-//  6. the ids are written out with 16-byte stores, and, when asked for, the similarities in
-//     the same order (W[v][u] as float32, -0.0 written as +0.0).
+// One workgroup sorts one row at a time, entirely in LDS, by a stable least-significant-
+// digit radix sort of 32-bit keys k = ~ord(W[v][u]) ("larger similarity" is "smaller key"),
+// four passes of 8 bits. The row is loaded in ascending u, and every pass is stable, so
+// equal keys come out in ascending u: the (value desc, id asc) order exactly, whatever the
+// distribution of values, with no data-dependent work.
+//
+// Element slots: wave w holds positions [w*EPT*64, (w+1)*EPT*64), position w*EPT*64 +
+// e*64 + lane in register e of that lane. One pass:
+//  1. for each register e in order, lanes with the same digit are found with eight ballots;
+//     they add their count to the wave's digit counter in LDS (all of them write the same
+//     new value), and each gets its offset (counter before the add + its rank among them);
+//  2. an exclusive scan over the counters in (digit, wave) order gives every (digit,
+//     wave) its base;
+//  3. every element is written to LDS at base + offset, then read back in position order.
+// Slots past the row hold the key of -inf and id 0xffff; they sort last and fill the
+// row's padding to a multiple of 8. Workgroups are persistent: each one loads the next row
+// of its share into registers while it sorts the current one. Barriers wait on LDS only,
+// so that prefetch stays in flight across them.
 #include "common.h"
 #include "internal.h"
 
 namespace tmfg {
 
 namespace {
-constexpr int kSamples = 256;
-constexpr int kRankMax = 32;
-constexpr int kMaxBig = kMaxN / (kRankMax + 1) + 1;
-}  // namespace
+constexpr int kPasses = 4;
+constexpr int kDigits = 256;
+constexpr int kHistStride = kDigits + 1;        // per-wave counters, padded against bank conflicts
+constexpr uint32_t kPadKey = 0xff800000u;       // ~ord(-inf): above every finite key
 
-// Bitonic sort of keys/ids[0..sz) in LDS by (key asc, id asc), one wave, no workgroup
-// barrier. All comparators move the smaller element to the lower index; positions past sz
-// act as +infinity and never move, so the network needs no padding storage.
-__device__ void wave_bitonic(uint32_t* k, uint16_t* id, int sz, int lane) {
-  int P = 1;
-  while (P < sz) P <<= 1;
-  for (int blk = 2; blk <= P; blk <<= 1) {
-    for (int j = blk >> 1; j > 0; j >>= 1) {
-      for (int i = lane; i < sz; i += kWave) {
-        const int l = (j == (blk >> 1)) ? (i ^ (blk - 1)) : (i ^ j);
-        if (l > i && l < sz) {
-          const uint32_t ki = k[i], kl = k[l];
-          const uint16_t ii = id[i], il = id[l];
-          if (kl < ki || (kl == ki && il < ii)) {
-            k[i] = kl;
-            k[l] = ki;
-            id[i] = il;
-            id[l] = ii;
-          }
-        }
-      }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-    }
-  }
+__device__ __forceinline__ void lds_barrier() {
+  // LDS traffic only: a workgroup barrier that does not wait for global loads in flight
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 template <int BLOCK, int EPT>
-__device__ void sort_row(const float* __restrict__ W, int n, uint16_t* __restrict__ idx, float* __restrict__ vals,
-                         int64_t ldi, int sub_log2, int v, uint8_t* smem) {
-  constexpr int NWAVE = BLOCK / kWave;
-  __shared__ uint32_t red_lo[NWAVE], red_hi[NWAVE];
-  __shared__ int nbig;
-  __shared__ int big_list[kMaxBig];
+struct RowSort {
+  static constexpr int NW = BLOCK / kWave;
+  static constexpr int CAP = BLOCK * EPT;        // slots per row
+  static constexpr int WS = EPT * kWave;         // slots per wave
+  static constexpr size_t lds_bytes() {
+    return (size_t)CAP * 4 + (size_t)CAP * 2 + (size_t)NW * kHistStride * 4 + 64 * 4;
+  }
+};
 
+// Global loads of one row into registers (raw similarities, position order).
+template <int BLOCK, int EPT>
+__device__ __forceinline__ void load_row(const float* __restrict__ W, int n, int v, float (&raw)[EPT]) {
+  const int m = n - 1;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const float* row = W + (size_t)v * n;
+  // slots past the row read the row's last element (a valid address; the value is unused),
+  // so that every load is unconditional
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int p = wave * RowSort<BLOCK, EPT>::WS + e * kWave + lane;
+    const int j = p < v ? p : p + 1;
+    raw[e] = row[j < m ? j : m];
+  }
+}
+
+// Keys and ids of one row from its similarities (position order).
+template <int BLOCK, int EPT>
+__device__ __forceinline__ void row_keys(const float (&raw)[EPT], int n, int v, uint32_t (&key)[EPT],
+                                         uint32_t (&idp)[EPT]) {
+  const int m = n - 1;
+  const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const int p = wave * RowSort<BLOCK, EPT>::WS + e * kWave + lane;
+    const int j = p < v ? p : p + 1;
+    // branch-free select: slots past the row get the padding key and id
+    const uint32_t in = 0u - (uint32_t)(p < m);
+    key[e] = (~ord_f32(raw[e]) & in) | (kPadKey & ~in);
+    idp[e] = ((uint32_t)j & in) | (0xffffu & ~in);
+  }
+}
+
+// Sorts one row given as keys and ids (idp: id in the low 16 bits) and writes ids (and
+// values) out.
+template <int BLOCK, int EPT>
+__device__ __forceinline__ void sort_row_keys(uint32_t (&key)[EPT], uint32_t (&idp)[EPT], int n, int v, uint16_t* __restrict__ idx,
+                              float* __restrict__ vals, int64_t ldi, uint8_t* smem) {
+  using RS = RowSort<BLOCK, EPT>;
+  constexpr int NW = RS::NW, CAP = RS::CAP, WS = RS::WS;
   const int m = n - 1;
   const int m_al = (m + 7) & ~7;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int S = m < kSamples ? m : kSamples;
-  const int SUB = 1 << sub_log2;
-  const int NB = (S + 1) * SUB;
+  const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
+  uint32_t* bkey = (uint32_t*)smem;                         // CAP
+  uint16_t* bid = (uint16_t*)(bkey + CAP);                  // CAP
+  uint32_t* hist = (uint32_t*)(bid + CAP);                  // NW x kHistStride
+  uint32_t* wsum = hist + NW * kHistStride;                 // 64
+  uint32_t* myh = hist + wave * kHistStride;
+  const uint64_t below = (1ull << lane) - 1ull;
+  // idp: low 16 bits the id, high 16 bits the element's offset in the current pass
 
-  uint32_t* keys = (uint32_t*)smem;             // m_al
-  uint16_t* ids = (uint16_t*)(keys + m_al);     // m_al
-  uint32_t* cnt = (uint32_t*)(ids + m_al);      // NB
-  uint32_t* spl = cnt + NB;                     // S
-
-  const float* row = W + (size_t)v * n;
-
-  // 1. the row into registers
-  uint32_t dk[EPT];
-  uint32_t lmin = 0xffffffffu, lmax = 0u;
+  for (int pass = 0; pass < kPasses; ++pass) {
+    const int shift = 8 * pass;
+    for (int i = tid; i < NW * kHistStride; i += BLOCK) hist[i] = 0;
+    lds_barrier();
+    // 1. per-wave digit counts and each element's offset inside (digit, wave)
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int j = e * BLOCK + tid;
-    if (j < n && j != v) {
-      dk[e] = ~ord_f32(row[j]);
-      lmin = min(lmin, dk[e]);
-      lmax = max(lmax, dk[e]);
-    }
-  }
-  lmin = wave_min_u32(lmin);
-  lmax = wave_max_u32(lmax);
-  if (lane == 0) {
-    red_lo[wave] = lmin;
-    red_hi[wave] = lmax;
-  }
-  for (int i = tid; i < NB; i += BLOCK) cnt[i] = 0;
-  if (tid == 0) nbig = 0;
-  // 2. samples: element position floor(i*m/S) of the row without v
-  if (tid < S) {
-    const int pos = (int)(((int64_t)tid * m) / S);
-    const int j = pos < v ? pos : pos + 1;
-    keys[tid] = ~ord_f32(row[j]);
-  }
-  __syncthreads();
-  uint32_t kmin = red_lo[0], kmax = red_hi[0];
-  for (int w = 1; w < NWAVE; ++w) {
-    kmin = min(kmin, red_lo[w]);
-    kmax = max(kmax, red_hi[w]);
-  }
-  if (tid < S) {
-    const uint32_t s = keys[tid];
-    int r = 0;
-    for (int q = 0; q < S; ++q) {
-      const uint32_t kq = keys[q];
-      r += (kq < s) || (kq == s && q < tid);
-    }
-    spl[r] = s;
-  }
-  __syncthreads();
-
-  // 3a. bucket of every element, histogram
-  uint32_t bk[EPT];
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t d = (key[e] >> shift) & 0xffu;
+      // lanes whose digit equals mine: for every bit, keep the lanes that agree with my bit
+      // (ballot XOR my bit spread over 32 bits has a 1 exactly where a lane disagrees)
+      uint32_t plo = ~0u, phi = ~0u;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int j = e * BLOCK + tid;
-    if (j < n && j != v) {
-      const uint32_t k = dk[e];
-      int lo = 0, len = S;                       // first splitter > k
-      while (len > 0) {
-        const int half = len >> 1;
-        if (spl[lo + half] <= k) {
-          lo += half + 1;
-          len -= half + 1;
-        } else {
-          len = half;
-        }
+      for (int b = 0; b < 8; ++b) {
+        const uint32_t sb = (uint32_t)__builtin_amdgcn_sbfe((int32_t)d, b, 1);   // 0 or ~0
+        const uint64_t bb = __ballot(sb != 0u);
+        plo &= ~((uint32_t)bb ^ sb);
+        phi &= ~((uint32_t)(bb >> 32) ^ sb);
       }
-      const uint64_t blo = lo > 0 ? spl[lo - 1] : kmin;
-      const uint64_t bhi = lo < S ? (uint64_t)spl[lo] : (uint64_t)kmax + 1;
-      const uint32_t sub = (uint32_t)((((uint64_t)k - blo) << sub_log2) / (bhi - blo));
-      bk[e] = (uint32_t)lo * SUB + sub;
-      atomicAdd(&cnt[bk[e]], 1u);
+      const uint64_t peers = ((uint64_t)phi << 32) | plo;
+      const uint32_t rank = (uint32_t)__popcll(peers & below);
+      const uint32_t old = myh[d];
+      myh[d] = old + (uint32_t)__popcll(peers);      // every peer writes the same value
+      idp[e] = ((old + rank) << 16) | (idp[e] & 0xffffu);
+      // materialise the offset now, so that the loaded counter and its address die here
+      asm volatile("" : "+v"(idp[e]));
     }
-  }
-  __syncthreads();
-
-  // 3b. exclusive scan of the histogram (contiguous chunk per thread, then across threads)
-  {
-    const int per = (NB + BLOCK - 1) / BLOCK;
-    const int b0 = tid * per;
-    uint32_t local = 0;
-    for (int i = 0; i < per; ++i)
-      if (b0 + i < NB) local += cnt[b0 + i];
-    // inclusive scan of 'local' across the workgroup
-    uint32_t x = local;
+    lds_barrier();
+    // 2. exclusive scan in (digit, wave) order: thread t takes 4 consecutive counters
+    {
+      uint32_t c[4], s = 0;
 #pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const uint32_t y = __shfl_up(x, off, kWave);
-      if (lane >= off) x += y;
-    }
-    if (lane == 63) red_lo[wave] = x;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int w = 0; w < wave; ++w) base += red_lo[w];
-    uint32_t run = base + x - local;
-    for (int i = 0; i < per; ++i)
-      if (b0 + i < NB) {
-        const uint32_t c = cnt[b0 + i];
-        cnt[b0 + i] = run;
-        run += c;
+      for (int i = 0; i < 4; ++i) {
+        const int g = 4 * tid + i;                 // g = d * NW + w
+        c[i] = hist[(g % NW) * kHistStride + g / NW];
+        s += c[i];
       }
-  }
-  __syncthreads();
-
-  // 3c. scatter; afterwards cnt[b] is the end of bucket b
+      uint32_t x = s;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    const int j = e * BLOCK + tid;
-    if (j < n && j != v) {
-      const uint32_t p = atomicAdd(&cnt[bk[e]], 1u);
-      keys[p] = dk[e];
-      ids[p] = (uint16_t)j;
-    }
-  }
-  __syncthreads();
-
-  // 4. exact position inside small buckets
-  int fin[EPT];
+      for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off, kWave);
+        if (lane >= off) x += y;
+      }
+      if (lane == kWave - 1) wsum[wave] = x;
+      lds_barrier();
+      uint32_t base = 0;
+      for (int w = 0; w < wave; ++w) base += wsum[w];
+      uint32_t run = base + x - s;
 #pragma unroll
-  for (int e = 0; e < EPT; ++e) {
-    fin[e] = -1;
-    const int j = e * BLOCK + tid;
-    if (j < n && j != v) {
-      const uint32_t b = bk[e];
-      const int s = b ? (int)cnt[b - 1] : 0;
-      const int en = (int)cnt[b];
-      const uint32_t k = dk[e];
-      if (en - s <= kRankMax) {
-        int r = 0;
-        for (int q = s; q < en; ++q) {
-          const uint32_t kq = keys[q];
-          r += (kq < k) || (kq == k && (int)ids[q] < j);
-        }
-        fin[e] = s + r;
-      } else if ((int)ids[s] == j) {
-        big_list[atomicAdd(&nbig, 1)] = (int)b;
+      for (int i = 0; i < 4; ++i) {
+        const int g = 4 * tid + i;
+        hist[(g % NW) * kHistStride + g / NW] = run;
+        run += c[i];
       }
     }
-  }
-  __syncthreads();
+    lds_barrier();
+    // 3. scatter, then read back in position order (the digit address is recomputed
+    //    rather than kept alive from step 1)
 #pragma unroll
-  for (int e = 0; e < EPT; ++e)
-    if (fin[e] >= 0) {
-      ids[fin[e]] = (uint16_t)(e * BLOCK + tid);
-      keys[fin[e]] = dk[e];
+    for (int e = 0; e < EPT; ++e) asm volatile("" : "+v"(key[e]));
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const uint32_t pos = myh[(key[e] >> shift) & 0xffu] + (idp[e] >> 16);
+      bkey[pos] = key[e];
+      bid[pos] = (uint16_t)idp[e];
     }
-  for (int i = m + tid; i < m_al; i += BLOCK) {
-    ids[i] = 0xffff;
-    keys[i] = 0xff800000u;              // -inf
+    lds_barrier();
+    if (pass + 1 < kPasses) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const int p = wave * WS + e * kWave + lane;
+        key[e] = bkey[p];
+        idp[e] = bid[p];
+      }
+      lds_barrier();      // every read of this pass's layout and counters is done
+    }
   }
-  __syncthreads();
 
-  // 5. large buckets
-  for (int q = wave; q < nbig; q += NWAVE) {
-    const int b = big_list[q];
-    const int s = b ? (int)cnt[b - 1] : 0;
-    wave_bitonic(keys + s, ids + s, (int)cnt[b] - s, lane);
-  }
-  __syncthreads();
-
-  // 6. write out
+  // 4. write out: ids with 16-byte stores, values (-0.0 already +0.0) beside them
   uint4* dst = (uint4*)(idx + (size_t)v * ldi);
-  const uint4* src = (const uint4*)ids;
+  const uint4* src = (const uint4*)bid;
   for (int i = tid; i < m_al / 8; i += BLOCK) dst[i] = src[i];
   if (vals) {
     float4* vdst = (float4*)(vals + (size_t)v * ldi);
     for (int i = tid; i < m_al / 4; i += BLOCK) {
-      const uint4 k = ((const uint4*)keys)[i];
+      const uint4 k = ((const uint4*)bkey)[i];
       vdst[i] = make_float4(unord_f32(~k.x), unord_f32(~k.y), unord_f32(~k.z), unord_f32(~k.w));
     }
   }
+  lds_barrier();          // the next row may overwrite the buffers
 }
+}  // namespace
 
-__host__ __device__ inline int sort_sub_log2(int n) {
-  const int m = n - 1;
-  const int S = m < kSamples ? m : kSamples;
-  int s = 0;
-  while (s < 5 && (int64_t)(S + 1) * (2 << s) * 2 <= m) ++s;
-  return s;
-}
-
+// Rows first, first + step, ... below n, each sorted in turn; the next row's similarities
+// are loaded while the current one is sorted.
 template <int BLOCK, int EPT>
 __global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restrict__ W, int n,
                                                           uint16_t* __restrict__ idx, float* __restrict__ vals,
-                                                          int64_t ldi, int sub_log2) {
+                                                          int64_t ldi) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  sort_row<BLOCK, EPT>(W, n, idx, vals, ldi, sub_log2, blockIdx.x, smem);
+  float raw[EPT];
+  uint32_t key[EPT], idp[EPT];
+  int v = blockIdx.x;
+  if (v < n) load_row<BLOCK, EPT>(W, n, v, raw);
+  for (; v < n; v += gridDim.x) {
+    row_keys<BLOCK, EPT>(raw, n, v, key, idp);
+    if (v + (int)gridDim.x < n) load_row<BLOCK, EPT>(W, n, v + gridDim.x, raw);
+    sort_row_keys<BLOCK, EPT>(key, idp, n, v, idx, vals, ldi, smem);
+  }
 }
 
+// Batched form: work units are the rows of every listed job (prefix sums of n).
 template <int BLOCK, int EPT>
 __global__ __launch_bounds__(BLOCK) void batch_sort_kernel(const BatchJob* __restrict__ jobs,
                                                            const int* __restrict__ list,
                                                            const int* __restrict__ prefix, int nlist, int total) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  const int unit = blockIdx.x;
-  if (unit >= total) return;
-  const int i = find_unit(prefix, nlist, unit);
-  const BatchJob& J = jobs[list[i]];
-  sort_row<BLOCK, EPT>(J.W, J.n, J.idx, J.vals, J.ldi, sort_sub_log2(J.n), unit - prefix[i], smem);
+  float raw[EPT];
+  uint32_t key[EPT], idp[EPT];
+  int u = blockIdx.x;
+  const BatchJob* J = nullptr;
+  int v = 0;
+  if (u < total) {
+    const int i = find_unit(prefix, nlist, u);
+    J = &jobs[list[i]];
+    v = u - prefix[i];
+    load_row<BLOCK, EPT>(J->W, J->n, v, raw);
+  }
+  for (; u < total; u += gridDim.x) {
+    const BatchJob* Jc = J;
+    const int vc = v;
+    row_keys<BLOCK, EPT>(raw, Jc->n, vc, key, idp);
+    const int u2 = u + (int)gridDim.x;
+    if (u2 < total) {
+      const int i = find_unit(prefix, nlist, u2);
+      J = &jobs[list[i]];
+      v = u2 - prefix[i];
+      load_row<BLOCK, EPT>(J->W, J->n, v, raw);
+    }
+    sort_row_keys<BLOCK, EPT>(key, idp, Jc->n, vc, Jc->idx, Jc->vals, Jc->ldi, smem);
+  }
 }
 
 namespace {
-size_t sort_lds_bytes(int n, int sub_log2) {
-  const int m = n - 1;
-  const int m_al = (m + 7) & ~7;
-  const int S = m < kSamples ? m : kSamples;
-  const int NB = (S + 1) << sub_log2;
-  return (size_t)m_al * 6 + (size_t)NB * 4 + (size_t)S * 4;
-}
+constexpr int kClasses = 8;
+// (BLOCK, EPT) of each size class; a class sorts rows of up to BLOCK * EPT + 1 vertices.
+constexpr int kClassBlock[kClasses] = {256, 256, 512, 1024, 1024, 1024, 1024, 1024};
+constexpr int kClassEpt[kClasses] = {1, 4, 4, 4, 8, 12, 16, 20};
+int g_cus = 0;
+int g_occ_rows[kClasses], g_occ_batch[kClasses];
+
 template <int BLOCK, int EPT>
-hipError_t launch_sort_t(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
-  const int sl = sort_sub_log2(n);
-  const size_t lds = sort_lds_bytes(n, sl);
-  hipLaunchKernelGGL((sort_rows_kernel<BLOCK, EPT>), dim3(n), dim3(BLOCK), lds, s, W, n, idx, vals, ldi, sl);
+hipError_t sort_attr_t(int c) {
+  const size_t lds = RowSort<BLOCK, EPT>::lds_bytes();
+  const void* ks[2] = {(const void*)sort_rows_kernel<BLOCK, EPT>, (const void*)batch_sort_kernel<BLOCK, EPT>};
+  int* occ[2] = {&g_occ_rows[c], &g_occ_batch[c]};
+  for (int k = 0; k < 2; ++k) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, ks[k]);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(ks[k], hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(occ[k], ks[k], BLOCK, lds);
+    if (e != hipSuccess) return e;
+    if (*occ[k] < 1) *occ[k] = 1;
+  }
+  return hipSuccess;
+}
+
+int grid_for(int rows, int occ) {
+  const int cap = (g_cus > 0 ? g_cus : 256) * occ;
+  return rows < cap ? rows : cap;
+}
+
+template <int BLOCK, int EPT>
+hipError_t launch_sort_t(int c, const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
+  hipLaunchKernelGGL((sort_rows_kernel<BLOCK, EPT>), dim3(grid_for(n, g_occ_rows[c])), dim3(BLOCK),
+                     (RowSort<BLOCK, EPT>::lds_bytes()), s, W, n, idx, vals, ldi);
+  return hipGetLastError();
+}
+
+template <int BLOCK, int EPT>
+hipError_t launch_batch_sort_t(int c, const BatchJob* jobs, const int* list, const int* prefix, int nlist,
+                               int total, hipStream_t s) {
+  hipLaunchKernelGGL((batch_sort_kernel<BLOCK, EPT>), dim3(grid_for(total, g_occ_batch[c])), dim3(BLOCK),
+                     (RowSort<BLOCK, EPT>::lds_bytes()), s, jobs, list, prefix, nlist, total);
   return hipGetLastError();
 }
 }  // namespace
 
 int64_t sort_row_stride(int n) { return round_up(n - 1 > 0 ? n - 1 : 1, 8); }
 
-template <int BLOCK, int EPT>
-hipError_t launch_batch_sort_t(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
-                               int n_max, hipStream_t s) {
-  const size_t lds = sort_lds_bytes(n_max, sort_sub_log2(n_max));
-  hipLaunchKernelGGL((batch_sort_kernel<BLOCK, EPT>), dim3(total), dim3(BLOCK), lds, s, jobs, list, prefix, nlist,
-                     total);
-  return hipGetLastError();
-}
-
-// Let every sort kernel use all of the LDS the static arrays leave free (set once).
-template <int BLOCK, int EPT>
-hipError_t sort_attr_t() {
-  const void* ks[2] = {(const void*)sort_rows_kernel<BLOCK, EPT>, (const void*)batch_sort_kernel<BLOCK, EPT>};
-  for (const void* k : ks) {
-    hipFuncAttributes a;
-    hipError_t e = hipFuncGetAttributes(&a, k);
-    if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
-
+// Kernel attributes and occupancies, set once per process (on the current device).
 hipError_t sort_init_attributes() {
+  int dev = 0;
   hipError_t e;
-  if ((e = sort_attr_t<256, 1>()) != hipSuccess) return e;
-  if ((e = sort_attr_t<256, 4>()) != hipSuccess) return e;
-  if ((e = sort_attr_t<512, 4>()) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 4>()) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 8>()) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 12>()) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 16>()) != hipSuccess) return e;
-  return sort_attr_t<1024, 20>();
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+  if ((e = sort_attr_t<256, 1>(0)) != hipSuccess) return e;
+  if ((e = sort_attr_t<256, 4>(1)) != hipSuccess) return e;
+  if ((e = sort_attr_t<512, 4>(2)) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 4>(3)) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 8>(4)) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 12>(5)) != hipSuccess) return e;
+  if ((e = sort_attr_t<1024, 16>(6)) != hipSuccess) return e;
+  return sort_attr_t<1024, 20>(7);
 }
 
+// The smallest class whose slots hold a row of n - 1 entries padded to a multiple of 8.
 int sort_class(int n) {
-  if (n <= 256) return 0;
-  if (n <= 1024) return 1;
-  if (n <= 2048) return 2;
-  if (n <= 4096) return 3;
-  if (n <= 8192) return 4;
-  if (n <= 12288) return 5;
-  if (n <= 16384) return 6;
-  return 7;
+  const int m_al = (int)round_up(n - 1 > 0 ? n - 1 : 1, 8);
+  for (int c = 0; c < kClasses; ++c)
+    if (m_al <= kClassBlock[c] * kClassEpt[c]) return c;
+  return kClasses - 1;
 }
 
 hipError_t launch_batch_sort(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
                              int n_max, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  switch (sort_class(n_max)) {
-    case 0: return launch_batch_sort_t<256, 1>(jobs, list, prefix, nlist, total, n_max, s);
-    case 1: return launch_batch_sort_t<256, 4>(jobs, list, prefix, nlist, total, n_max, s);
-    case 2: return launch_batch_sort_t<512, 4>(jobs, list, prefix, nlist, total, n_max, s);
-    case 3: return launch_batch_sort_t<1024, 4>(jobs, list, prefix, nlist, total, n_max, s);
-    case 4: return launch_batch_sort_t<1024, 8>(jobs, list, prefix, nlist, total, n_max, s);
-    case 5: return launch_batch_sort_t<1024, 12>(jobs, list, prefix, nlist, total, n_max, s);
-    case 6: return launch_batch_sort_t<1024, 16>(jobs, list, prefix, nlist, total, n_max, s);
-    default: return launch_batch_sort_t<1024, 20>(jobs, list, prefix, nlist, total, n_max, s);
+  const int c = sort_class(n_max);
+  switch (c) {
+    case 0: return launch_batch_sort_t<256, 1>(c, jobs, list, prefix, nlist, total, s);
+    case 1: return launch_batch_sort_t<256, 4>(c, jobs, list, prefix, nlist, total, s);
+    case 2: return launch_batch_sort_t<512, 4>(c, jobs, list, prefix, nlist, total, s);
+    case 3: return launch_batch_sort_t<1024, 4>(c, jobs, list, prefix, nlist, total, s);
+    case 4: return launch_batch_sort_t<1024, 8>(c, jobs, list, prefix, nlist, total, s);
+    case 5: return launch_batch_sort_t<1024, 12>(c, jobs, list, prefix, nlist, total, s);
+    case 6: return launch_batch_sort_t<1024, 16>(c, jobs, list, prefix, nlist, total, s);
+    default: return launch_batch_sort_t<1024, 20>(c, jobs, list, prefix, nlist, total, s);
   }
 }
 
 hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
-  if (n <= 256) return launch_sort_t<256, 1>(W, n, idx, vals, ldi, s);
-  if (n <= 1024) return launch_sort_t<256, 4>(W, n, idx, vals, ldi, s);
-  if (n <= 2048) return launch_sort_t<512, 4>(W, n, idx, vals, ldi, s);
-  if (n <= 4096) return launch_sort_t<1024, 4>(W, n, idx, vals, ldi, s);
-  if (n <= 8192) return launch_sort_t<1024, 8>(W, n, idx, vals, ldi, s);
-  if (n <= 12288) return launch_sort_t<1024, 12>(W, n, idx, vals, ldi, s);
-  if (n <= 16384) return launch_sort_t<1024, 16>(W, n, idx, vals, ldi, s);
-  return launch_sort_t<1024, 20>(W, n, idx, vals, ldi, s);
+  const int c = sort_class(n);
+  switch (c) {
+    case 0: return launch_sort_t<256, 1>(c, W, n, idx, vals, ldi, s);
+    case 1: return launch_sort_t<256, 4>(c, W, n, idx, vals, ldi, s);
+    case 2: return launch_sort_t<512, 4>(c, W, n, idx, vals, ldi, s);
+    case 3: return launch_sort_t<1024, 4>(c, W, n, idx, vals, ldi, s);
+    case 4: return launch_sort_t<1024, 8>(c, W, n, idx, vals, ldi, s);
+    case 5: return launch_sort_t<1024, 12>(c, W, n, idx, vals, ldi, s);
+    case 6: return launch_sort_t<1024, 16>(c, W, n, idx, vals, ldi, s);
+    default: return launch_sort_t<1024, 20>(c, W, n, idx, vals, ldi, s);
+  }
 }
 
 }  // namespace tmfg
