@@ -51,8 +51,10 @@ constexpr int kSpan = kScan * kGroup;            // list positions scanned per r
 constexpr int kCand = 8;                         // candidates taken per list and round
 constexpr int kSkipLoads = 4;                    // 16-byte loads per lane in a skip scan
 constexpr int kMaxRounds = 64;
-constexpr int kMaxWork = 128;                    // faces recomputed per selection phase
-constexpr int kMaxSel = 16;                      // chunks loaded per selection phase
+constexpr int kMaxWork = 256;                    // faces recomputed per selection phase
+constexpr int kMaxSel = 48;                      // chunks loaded per selection phase
+constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
+static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
 // Time the sub-steps of one walk group (stats [16..19]); the waits it adds slow that group.
 constexpr bool kWalkDiag = false;
 
@@ -581,11 +583,21 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // stale record ranked above the floor, which is queued for recomputation.
     const int nsel = s_nsel, nnew = s_nnew;
     const uint64_t floor = s_floor;
-    for (int sl = wave; sl < nsel; sl += kWaves) {
+    // all of this wave's records are requested before any is used (one trip to memory)
+    uint4 crecs[kSelPerWave];
+#pragma unroll
+    for (int i = 0; i < kSelPerWave; ++i) {
+      const int sl = wave + i * kWaves;
+      const int f = (sl < nsel ? sel[sl] : 0) * 64 + lane;
+      crecs[i] = P.frec[f < nf ? f : nf - 1];
+    }
+#pragma unroll
+    for (int i = 0; i < kSelPerWave; ++i) {
+      const int sl = wave + i * kWaves;
+      if (sl >= nsel) break;
       const int f = sel[sl] * 64 + lane;
-      uint4 crec = make_uint4(0, 0, 0, 0);
+      const uint4 crec = f < nf ? crecs[i] : make_uint4(0, 0, 0, 0);
       int link = -1;
-      if (f < nf) crec = P.frec[f];
       for (int q = 0; q < nnew; ++q)
         if (work[q].f == f) link = q;
       if (link < 0 && s_ins < n) {
