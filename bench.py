@@ -189,27 +189,37 @@ def _lazy_prefix(W: np.ndarray, k: int) -> None:
 
 def bench_batch(args):
     """512 independent instances (n log-uniform in [64, 4096], L uniform in [64, 512]) in one
-    graph replay, against the same instances built one per launch."""
+    graph replay with autotuned launch configurations, against the same batch with default
+    configurations and against the same instances built one per launch."""
     import torch
     import paper_2408_09399_amd as tm
     from paper_2408_09399_amd import synth
     inst = synth.config_c4(args.batch)
     dev = torch.device("cuda:0")
     Xs = [torch.from_numpy(s.X).to(dev) for s in inst]
-    batch = tm.Batch([("X", x) for x in Xs])
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        batch.run(stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        batch.run(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    bad = [i for i, r in enumerate(batch.results) if int(r.status.item()) != 0]
-    if bad:
-        print(json.dumps({"error": f"batch instances failed: {bad[:5]}"}))
-        sys.exit(1)
+
+    def timed(batch):
+        for _ in range(args.warmup):
+            batch.run(stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.run(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        bad = [i for i, r in enumerate(batch.results) if int(r.status.item()) != 0]
+        if bad:
+            print(json.dumps({"error": f"batch instances failed: {bad[:5]}"}))
+            sys.exit(1)
+        return wall
+
+    default = tm.Batch([("X", x) for x in Xs])
+    wall_default = timed(default)
+    default.close()
+    batch = tm.Batch([("X", x) for x in Xs], flags=tm.BATCH_AUTOTUNE)
+    tuned_cfg = batch.config()
+    wall = timed(batch)
     # the same instances, one build (one launch sequence) each, back to back on one plan
     n_max = max(s.X.shape[0] for s in inst)
     L_max = max(s.X.shape[1] for s in inst)
@@ -234,6 +244,9 @@ def bench_batch(args):
                                f"L uniform in [64, 512]", "instances": len(inst),
                    "sum_n": int(sum(s.X.shape[0] for s in inst))},
         "insertions_per_s": round(insertions / per, 1),
+        "autotuned": tuned_cfg,
+        "default_launch": {"ms_per_step": round(wall_default / args.steps * 1e3, 3),
+                           "builds_per_s": round(len(inst) * args.steps / wall_default, 2)},
         "plain_one_per_launch": {"seconds": round(plain, 3), "builds_per_s": round(len(inst) / plain, 2)},
         "speedup_vs_plain": round(plain / per, 2),
     }

@@ -66,7 +66,8 @@ typedef enum {
 enum {
   TMFG_NO_VALIDATE = 1u << 0,   /* skip the finite / bitwise-symmetry check of a caller W */
   TMFG_TIMING = 1u << 1,        /* record per-phase HIP events (tmfg_plan_phase_ms) */
-  TMFG_BATCH_NO_GRAPH = 1u << 2 /* batch: launch the kernels directly instead of a graph */
+  TMFG_BATCH_NO_GRAPH = 1u << 2, /* batch: launch the kernels directly instead of a graph */
+  TMFG_BATCH_AUTOTUNE = 1u << 3  /* batch: pick launch configurations by timing them at creation */
 };
 
 typedef struct tmfg_plan_s* tmfg_plan;
@@ -128,7 +129,7 @@ tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
    phase as one grouped launch over all instances, and the insertion loops as one
    persistent launch whose workgroups take instances largest first. Each instance gets the
    result tmfg_build would give it, bit for bit. Flags: TMFG_NO_VALIDATE,
-   TMFG_BATCH_NO_GRAPH. */
+   TMFG_BATCH_NO_GRAPH, TMFG_BATCH_AUTOTUNE. */
 tmfg_status tmfg_batch_create(tmfg_batch* batch, const tmfg_job* jobs, int32_t count, uint32_t flags);
 
 /* Run (replay) the batch on `stream`; the inputs may change between runs, the buffers may
@@ -137,6 +138,14 @@ tmfg_status tmfg_batch_run(tmfg_batch batch, hipStream_t stream);
 
 /* Release a batch (waits for the device). NULL is a no-op. */
 tmfg_status tmfg_batch_destroy(tmfg_batch batch);
+
+/* Launch configuration of a batch (with TMFG_BATCH_AUTOTUNE, the one the tuner chose by
+   timing each knob on the batch's inputs at creation; those inputs must then be valid):
+   [0..7] sort configuration index of each size class (-1: class absent), [8] rows per sort
+   workgroup (0: one resident fill of the device), [9] persistent loop workgroups,
+   [10] configurations timed, [11] milliseconds spent tuning, [12..15] reserved. The
+   configuration never changes results. */
+tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]);
 
 /* Device bytes a batch over these jobs holds; 0 if a job is invalid. */
 size_t tmfg_batch_footprint_bytes(const tmfg_job* jobs, int32_t count, uint32_t flags);

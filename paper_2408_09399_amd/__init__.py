@@ -5,8 +5,9 @@ include/tmfg.h); this package holds its ctypes binding and the seeded synthetic 
 generators. The library is loaded on first use, and a missing build raises.
 """
 from .binding import (Plan, Result, Batch, Server, TmfgError, build, correlation, sort_rows, seed, face_sweep,
-                      footprint_bytes, alloc_result, STATUS, NO_VALIDATE, TIMING, BATCH_NO_GRAPH, PENDING)
+                      footprint_bytes, alloc_result, STATUS, NO_VALIDATE, TIMING, BATCH_NO_GRAPH, BATCH_AUTOTUNE,
+                      PENDING)
 
 __all__ = ["Plan", "Result", "Batch", "Server", "TmfgError", "build", "correlation", "sort_rows", "seed",
            "face_sweep", "footprint_bytes", "alloc_result", "STATUS", "NO_VALIDATE", "TIMING",
-           "BATCH_NO_GRAPH", "PENDING"]
+           "BATCH_NO_GRAPH", "BATCH_AUTOTUNE", "PENDING"]

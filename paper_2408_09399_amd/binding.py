@@ -24,6 +24,7 @@ PENDING = 9
 NO_VALIDATE = 1 << 0
 TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
+BATCH_AUTOTUNE = 1 << 3
 
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -43,6 +44,7 @@ SIGNATURES = {
     "tmfg_batch_run": (_I, [_P, _P]),
     "tmfg_batch_destroy": (_I, [_P]),
     "tmfg_batch_footprint_bytes": (ctypes.c_size_t, [_P, _I, ctypes.c_uint32]),
+    "tmfg_batch_config": (_I, [_P, ctypes.POINTER(_I)]),
     "tmfg_build_batch": (_I, [_P, _P, _I, _P]),
     "tmfg_server_create": (_I, [ctypes.POINTER(_P), _P]),
     "tmfg_server_submit": (_I, [_P, _P, _I, _I, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
@@ -343,6 +345,14 @@ class Batch:
     def run(self, stream=None):
         _check(_lib().tmfg_batch_run(self._h, _stream(stream)), "tmfg_batch_run")
         return self.results
+
+    def config(self) -> dict:
+        """The launch configuration in use (see tmfg_batch_config)."""
+        out = (_I * 16)()
+        _check(_lib().tmfg_batch_config(self._h, out), "tmfg_batch_config")
+        v = list(out)
+        return {"sort_config": v[0:8], "sort_rows_per_wg": v[8], "loop_workgroups": v[9],
+                "tune_trials": v[10], "tune_ms": v[11]}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

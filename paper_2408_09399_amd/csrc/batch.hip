@@ -21,14 +21,15 @@
 
 namespace tmfg {
 
-__global__ void batch_reset_kernel(BatchJob* jobs, int count, int* queue_head) {
+__global__ void batch_reset_kernel(BatchJob* jobs, int count, int* queue_head, int clear_flags) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) *jobs[i].flags = 0;
+  if (clear_flags && i < count) *jobs[i].flags = 0;
   if (i == 0) *queue_head = 0;
 }
 
-hipError_t launch_batch_reset(BatchJob* jobs, int count, int* queue_head, hipStream_t s) {
-  hipLaunchKernelGGL(batch_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, jobs, count, queue_head);
+hipError_t launch_batch_reset(BatchJob* jobs, int count, int* queue_head, bool clear_flags, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3((count + 255) / 256), dim3(256), 0, s, jobs, count, queue_head,
+                     (int)clear_flags);
   return hipGetLastError();
 }
 
@@ -166,7 +167,7 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
   auto lp = [&](const GroupList& g) { return I + g.o_list; };
   auto pp = [&](const GroupList& g) { return I + g.o_prefix; };
   hipError_t e;
-  if ((e = launch_batch_reset(L.d_jobs, spec.count, L.d_queue, s)) != hipSuccess) return e;
+  if ((e = launch_batch_reset(L.d_jobs, spec.count, L.d_queue, true, s)) != hipSuccess) return e;
   if ((e = launch_batch_standardize(L.d_jobs, lp(spec.stdz), pp(spec.stdz), spec.stdz.nlist, spec.stdz.total, s)) !=
       hipSuccess)
     return e;
@@ -183,12 +184,23 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
   if ((e = launch_batch_seed(L.d_jobs, lp(spec.seed), pp(spec.seed), spec.seed.nlist, spec.seed.total, s)) !=
       hipSuccess)
     return e;
-  for (int c = 0; c < 8; ++c) {
-    const GroupList& g = spec.sort[c];
-    if (g.nlist == 0) continue;
-    if ((e = launch_batch_sort(L.d_jobs, lp(g), pp(g), g.nlist, g.total, g.n_max, s)) != hipSuccess) return e;
-  }
+  for (int c = 0; c < kSortClasses; ++c)
+    if ((e = batch_enqueue_sort(spec, L, c, s)) != hipSuccess) return e;
   return launch_batch_loop(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, nullptr, s);
+}
+
+hipError_t batch_enqueue_sort(const BatchSpec& spec, const BatchLaunch& L, int cls, hipStream_t s) {
+  const GroupList& g = spec.sort[cls];
+  if (g.nlist == 0) return hipSuccess;
+  return launch_batch_sort(L.d_jobs, L.d_ints + g.o_list, L.d_ints + g.o_prefix, g.nlist, g.total, g.n_max,
+                           L.sort_cfg[cls], L.sort_rows, s);
+}
+
+hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipStream_t s) {
+  hipError_t e;
+  // the queue only: error flags raised by the earlier phases stay, and stop their instances
+  if ((e = launch_batch_reset(L.d_jobs, spec.count, L.d_queue, false, s)) != hipSuccess) return e;
+  return launch_batch_loop(L.d_jobs, L.d_ints + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, nullptr, s);
 }
 
 hipError_t batch_grid(int device, int count, int n_max, int* grid) {
@@ -214,6 +226,8 @@ struct tmfg_batch_s {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<tmfg_job> jobs;   // the job set this batch was made for
+  int tune_trials = 0;          // autotuning: configurations timed, and milliseconds spent
+  float tune_ms = 0.0f;
 };
 
 namespace {
@@ -230,6 +244,104 @@ void batch_free(tmfg_batch b) {
 tmfg_status fail(hipError_t e) {
   tmfg::record_hip_error((int)e);
   return e == hipErrorOutOfMemory ? TMFG_E_NOMEM : TMFG_E_HIP;
+}
+
+// Best of `reps` timed runs of `enq` on `st`, after one untimed run.
+template <class F>
+hipError_t time_best(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, F enq, float* ms) {
+  hipError_t e;
+  if ((e = enq()) != hipSuccess) return e;
+  float best = 3.0e38f;
+  for (int r = 0; r < reps; ++r) {
+    if ((e = hipEventRecord(e0, st)) != hipSuccess || (e = enq()) != hipSuccess ||
+        (e = hipEventRecord(e1, st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess)
+      return e;
+    float t = 0.0f;
+    if ((e = hipEventElapsedTime(&t, e0, e1)) != hipSuccess) return e;
+    best = t < best ? t : best;
+  }
+  *ms = best;
+  return hipSuccess;
+}
+
+// Autotuning on the batch's own inputs: one full run puts every phase's inputs in place,
+// then each knob is timed on the phase it affects, one knob at a time, keeping a change only
+// when it is at least 2% faster:
+//   * the launch configuration (threads x slots per thread) of each size class's row sort;
+//   * the rows each sort workgroup takes (resident fill of the device, or 2, 4, 16 rows);
+//   * the number of persistent loop workgroups (all that fit, three quarters, half).
+// Results do not depend on any of these.
+hipError_t autotune(tmfg_batch b) {
+  tmfg::BatchLaunch& L = b->launch;
+  const tmfg::BatchSpec& S = b->spec;
+  hipStream_t st = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr, ea = nullptr, eb = nullptr;
+  hipError_t e;
+  if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess) return e;
+  if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess ||
+      (e = hipEventCreate(&ea)) != hipSuccess || (e = hipEventCreate(&eb)) != hipSuccess)
+    goto done;
+  if ((e = hipEventRecord(ea, st)) != hipSuccess) goto done;
+  if ((e = tmfg::batch_enqueue(S, L, st)) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess) goto done;
+  {
+    auto sorts = [&]() -> hipError_t {
+      for (int c = 0; c < tmfg::kSortClasses; ++c) {
+        const hipError_t r = tmfg::batch_enqueue_sort(S, L, c, st);
+        if (r != hipSuccess) return r;
+      }
+      return hipSuccess;
+    };
+    float best = 0.0f, t = 0.0f;
+    for (int c = 0; c < tmfg::kSortClasses; ++c) {
+      if (S.sort[c].nlist == 0) continue;
+      L.sort_cfg[c] = tmfg::sort_default_config(c);
+      auto one = [&]() { return tmfg::batch_enqueue_sort(S, L, c, st); };
+      if ((e = time_best(st, e0, e1, 2, one, &best)) != hipSuccess) goto done;
+      ++b->tune_trials;
+      for (int cfg = 0; cfg < tmfg::kSortConfigs; ++cfg) {
+        if (cfg == tmfg::sort_default_config(c) || !tmfg::sort_config_fits(cfg, c)) continue;
+        const int keep = L.sort_cfg[c];
+        L.sort_cfg[c] = cfg;
+        if ((e = time_best(st, e0, e1, 2, one, &t)) != hipSuccess) goto done;
+        ++b->tune_trials;
+        if (t < 0.98f * best) best = t;
+        else L.sort_cfg[c] = keep;
+      }
+    }
+    if ((e = time_best(st, e0, e1, 2, sorts, &best)) != hipSuccess) goto done;
+    ++b->tune_trials;
+    for (int rows : {2, 4, 16}) {
+      const int keep = L.sort_rows;
+      L.sort_rows = rows;
+      if ((e = time_best(st, e0, e1, 2, sorts, &t)) != hipSuccess) goto done;
+      ++b->tune_trials;
+      if (t < 0.98f * best) best = t;
+      else L.sort_rows = keep;
+    }
+    auto loops = [&]() { return tmfg::batch_enqueue_loop(S, L, st); };
+    if ((e = time_best(st, e0, e1, 2, loops, &best)) != hipSuccess) goto done;
+    ++b->tune_trials;
+    const int full = L.grid;
+    for (int g : {full * 3 / 4, full / 2}) {
+      if (g < 1 || g == full) continue;
+      const int keep = L.grid;
+      L.grid = g;
+      if ((e = time_best(st, e0, e1, 2, loops, &t)) != hipSuccess) goto done;
+      ++b->tune_trials;
+      if (t < 0.98f * best) best = t;
+      else L.grid = keep;
+    }
+  }
+  if ((e = hipEventRecord(eb, st)) != hipSuccess || (e = hipEventSynchronize(eb)) != hipSuccess) goto done;
+  e = hipEventElapsedTime(&b->tune_ms, ea, eb);
+done:
+  if (st) hipStreamSynchronize(st);
+  if (e0) hipEventDestroy(e0);
+  if (e1) hipEventDestroy(e1);
+  if (ea) hipEventDestroy(ea);
+  if (eb) hipEventDestroy(eb);
+  if (st) hipStreamDestroy(st);
+  return e;
 }
 
 }  // namespace
@@ -253,7 +365,7 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
   if (!out) return TMFG_E_INVALID;
   *out = nullptr;
   if (!jobs || count <= 0) return TMFG_E_INVALID;
-  if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_BATCH_NO_GRAPH)) return TMFG_E_INVALID;
+  if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_BATCH_NO_GRAPH | TMFG_BATCH_AUTOTUNE)) return TMFG_E_INVALID;
   tmfg::BatchSpec spec;
   const tmfg_status st = tmfg::batch_describe(jobs, count, flags, spec);
   if (st != TMFG_OK) return st;
@@ -303,6 +415,11 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
     return fail(e);
   }
 
+  if ((flags & TMFG_BATCH_AUTOTUNE) && (e = autotune(b)) != hipSuccess) {
+    batch_free(b);
+    return fail(e);
+  }
+
   if (!(flags & TMFG_BATCH_NO_GRAPH)) {
     if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
@@ -336,6 +453,20 @@ tmfg_status tmfg_batch_destroy(tmfg_batch batch) {
   hipError_t e = hipDeviceSynchronize();
   batch_free(batch);
   if (e != hipSuccess) return fail(e);
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]) {
+  if (!batch || !out) return TMFG_E_INVALID;
+  for (int i = 0; i < 16; ++i) out[i] = 0;
+  for (int c = 0; c < tmfg::kSortClasses; ++c) {
+    const int cfg = batch->launch.sort_cfg[c];
+    out[c] = batch->spec.sort[c].nlist == 0 ? -1 : (cfg >= 0 ? cfg : tmfg::sort_default_config(c));
+  }
+  out[8] = batch->launch.sort_rows;
+  out[9] = batch->launch.grid;
+  out[10] = batch->tune_trials;
+  out[11] = (int32_t)(batch->tune_ms + 0.5f);
   return TMFG_OK;
 }
 

@@ -44,12 +44,18 @@ struct BatchLaunch {
   const int* d_ints = nullptr;
   int* d_queue = nullptr;
   int grid = 1;                                             // persistent loop workgroups
+  int sort_cfg[kSortClasses] = {-1, -1, -1, -1, -1, -1, -1, -1};   // -1: the class default
+  int sort_rows = 0;                                        // rows per sort workgroup (0: resident fill)
   std::vector<std::pair<const float*, float*>> w_copies;    // caller W -> W_out
   std::vector<size_t> w_copy_bytes;
 };
 
 // Enqueues every phase of the batch on `s` (no allocation, no synchronisation).
 hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_t s);
+// The row sorts of one size class alone, and the insertion loops alone (with the reset of
+// the status flags and the queue they need); inputs of each must already be in place.
+hipError_t batch_enqueue_sort(const BatchSpec& spec, const BatchLaunch& L, int cls, hipStream_t s);
+hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipStream_t s);
 
 // Persistent loop grid for `count` jobs of largest size n_max: the loop workgroups that
 // fit on the device at once, at most one per job.

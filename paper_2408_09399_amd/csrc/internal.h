@@ -77,7 +77,7 @@ struct BatchJob {
 // Grouped launches over the instances of a batch. Each takes a device list of job indices
 // and a device prefix array (prefix[i] = first unit of list[i], prefix[nlist] = total) of
 // the phase's work units: rows, tiles or columns; blocks find their job by binary search.
-hipError_t launch_batch_reset(BatchJob* jobs, int count, int* queue_head, hipStream_t s);
+hipError_t launch_batch_reset(BatchJob* jobs, int count, int* queue_head, bool clear_flags, hipStream_t s);
 hipError_t launch_batch_standardize(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
                                     hipStream_t s);
 hipError_t launch_batch_gemm(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
@@ -87,10 +87,15 @@ hipError_t launch_batch_validate(const BatchJob* jobs, const int* list, const in
 hipError_t launch_batch_seed(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
                              hipStream_t s);
 // All instances in one sort launch share a size class (sort_class(n)); n_max is the
-// largest n among them.
+// largest n among them. cfg selects the launch configuration (-1: the class default; see
+// sort_config_fits), rows_per_wg the persistent grid (0: one resident fill of the device).
+constexpr int kSortClasses = 8;
+constexpr int kSortConfigs = 12;
 hipError_t launch_batch_sort(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
-                             int n_max, hipStream_t s);
+                             int n_max, int cfg, int rows_per_wg, hipStream_t s);
 int sort_class(int n);
+int sort_default_config(int cls);
+bool sort_config_fits(int cfg, int cls);
 // Persistent insertion loops: `grid` workgroups take instances from `order` (device array
 // of job indices, largest first) through the counter at *queue_head.
 hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,

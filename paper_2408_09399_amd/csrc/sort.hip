@@ -242,12 +242,18 @@ __global__ __launch_bounds__(BLOCK) void batch_sort_kernel(const BatchJob* __res
 }
 
 namespace {
-constexpr int kClasses = 8;
-// (BLOCK, EPT) of each size class; a class sorts rows of up to BLOCK * EPT + 1 vertices.
-constexpr int kClassBlock[kClasses] = {256, 256, 512, 1024, 1024, 1024, 1024, 1024};
-constexpr int kClassEpt[kClasses] = {1, 4, 4, 4, 8, 12, 16, 20};
+// Launch configurations (BLOCK threads, EPT slots per thread): a row of n vertices fits a
+// configuration when its n - 1 entries, padded to a multiple of 8, fit in BLOCK * EPT slots.
+struct SortCfg {
+  int block, ept;
+};
+constexpr SortCfg kCfgs[kSortConfigs] = {{256, 1},  {256, 4},  {512, 2},   {512, 4},   {256, 8},   {1024, 4},
+                                         {512, 8},  {1024, 8}, {512, 16},  {1024, 12}, {1024, 16}, {1024, 20}};
+// Size classes (by slot count) and the configuration each one uses by default.
+constexpr int kClassCap[kSortClasses] = {256, 1024, 2048, 4096, 8192, 12288, 16384, 20480};
+constexpr int kClassDefault[kSortClasses] = {0, 1, 3, 5, 7, 9, 10, 11};
 int g_cus = 0;
-int g_occ_rows[kClasses], g_occ_batch[kClasses];
+int g_occ_rows[kSortConfigs], g_occ_batch[kSortConfigs];
 
 template <int BLOCK, int EPT>
 hipError_t sort_attr_t(int c) {
@@ -267,25 +273,32 @@ hipError_t sort_attr_t(int c) {
   return hipSuccess;
 }
 
-int grid_for(int rows, int occ) {
-  const int cap = (g_cus > 0 ? g_cus : 256) * occ;
-  return rows < cap ? rows : cap;
+// Persistent grid: `rows_per_wg` = 0 fills the device once (resident workgroups); a positive
+// value asks for about that many rows per workgroup instead (more, shorter-lived ones).
+int grid_for(int rows, int occ, int rows_per_wg) {
+  int g = (g_cus > 0 ? g_cus : 256) * occ;
+  if (rows_per_wg > 0) g = (rows + rows_per_wg - 1) / rows_per_wg;
+  return rows < g ? rows : (g < 1 ? 1 : g);
 }
 
 template <int BLOCK, int EPT>
 hipError_t launch_sort_t(int c, const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
-  hipLaunchKernelGGL((sort_rows_kernel<BLOCK, EPT>), dim3(grid_for(n, g_occ_rows[c])), dim3(BLOCK),
+  hipLaunchKernelGGL((sort_rows_kernel<BLOCK, EPT>), dim3(grid_for(n, g_occ_rows[c], 0)), dim3(BLOCK),
                      (RowSort<BLOCK, EPT>::lds_bytes()), s, W, n, idx, vals, ldi);
   return hipGetLastError();
 }
 
 template <int BLOCK, int EPT>
 hipError_t launch_batch_sort_t(int c, const BatchJob* jobs, const int* list, const int* prefix, int nlist,
-                               int total, hipStream_t s) {
-  hipLaunchKernelGGL((batch_sort_kernel<BLOCK, EPT>), dim3(grid_for(total, g_occ_batch[c])), dim3(BLOCK),
-                     (RowSort<BLOCK, EPT>::lds_bytes()), s, jobs, list, prefix, nlist, total);
+                               int total, int rows_per_wg, hipStream_t s) {
+  hipLaunchKernelGGL((batch_sort_kernel<BLOCK, EPT>), dim3(grid_for(total, g_occ_batch[c], rows_per_wg)),
+                     dim3(BLOCK), (RowSort<BLOCK, EPT>::lds_bytes()), s, jobs, list, prefix, nlist, total);
   return hipGetLastError();
 }
+
+#define TMFG_SORT_CFGS(X)                                                                                     \
+  X(0, 256, 1) X(1, 256, 4) X(2, 512, 2) X(3, 512, 4) X(4, 256, 8) X(5, 1024, 4) X(6, 512, 8) X(7, 1024, 8) \
+  X(8, 512, 16) X(9, 1024, 12) X(10, 1024, 16) X(11, 1024, 20)
 }  // namespace
 
 int64_t sort_row_stride(int n) { return round_up(n - 1 > 0 ? n - 1 : 1, 8); }
@@ -296,52 +309,51 @@ hipError_t sort_init_attributes() {
   hipError_t e;
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&g_cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
-  if ((e = sort_attr_t<256, 1>(0)) != hipSuccess) return e;
-  if ((e = sort_attr_t<256, 4>(1)) != hipSuccess) return e;
-  if ((e = sort_attr_t<512, 4>(2)) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 4>(3)) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 8>(4)) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 12>(5)) != hipSuccess) return e;
-  if ((e = sort_attr_t<1024, 16>(6)) != hipSuccess) return e;
-  return sort_attr_t<1024, 20>(7);
+#define X(i, b, t) \
+  if ((e = sort_attr_t<b, t>(i)) != hipSuccess) return e;
+  TMFG_SORT_CFGS(X)
+#undef X
+  return hipSuccess;
 }
 
 // The smallest class whose slots hold a row of n - 1 entries padded to a multiple of 8.
 int sort_class(int n) {
   const int m_al = (int)round_up(n - 1 > 0 ? n - 1 : 1, 8);
-  for (int c = 0; c < kClasses; ++c)
-    if (m_al <= kClassBlock[c] * kClassEpt[c]) return c;
-  return kClasses - 1;
+  for (int c = 0; c < kSortClasses; ++c)
+    if (m_al <= kClassCap[c]) return c;
+  return kSortClasses - 1;
+}
+
+int sort_default_config(int cls) { return kClassDefault[cls]; }
+
+// Whether configuration `cfg` holds rows of class `cls` (and is no more than twice its size).
+bool sort_config_fits(int cfg, int cls) {
+  const int cap = kCfgs[cfg].block * kCfgs[cfg].ept;
+  return cap >= kClassCap[cls] && cap <= 2 * kClassCap[cls];
 }
 
 hipError_t launch_batch_sort(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
-                             int n_max, hipStream_t s) {
+                             int n_max, int cfg, int rows_per_wg, hipStream_t s) {
   if (total <= 0) return hipSuccess;
-  const int c = sort_class(n_max);
-  switch (c) {
-    case 0: return launch_batch_sort_t<256, 1>(c, jobs, list, prefix, nlist, total, s);
-    case 1: return launch_batch_sort_t<256, 4>(c, jobs, list, prefix, nlist, total, s);
-    case 2: return launch_batch_sort_t<512, 4>(c, jobs, list, prefix, nlist, total, s);
-    case 3: return launch_batch_sort_t<1024, 4>(c, jobs, list, prefix, nlist, total, s);
-    case 4: return launch_batch_sort_t<1024, 8>(c, jobs, list, prefix, nlist, total, s);
-    case 5: return launch_batch_sort_t<1024, 12>(c, jobs, list, prefix, nlist, total, s);
-    case 6: return launch_batch_sort_t<1024, 16>(c, jobs, list, prefix, nlist, total, s);
-    default: return launch_batch_sort_t<1024, 20>(c, jobs, list, prefix, nlist, total, s);
+  if (cfg < 0) cfg = kClassDefault[sort_class(n_max)];
+  switch (cfg) {
+#define X(i, b, t) \
+  case i: return launch_batch_sort_t<b, t>(i, jobs, list, prefix, nlist, total, rows_per_wg, s);
+    TMFG_SORT_CFGS(X)
+#undef X
   }
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
-  const int c = sort_class(n);
-  switch (c) {
-    case 0: return launch_sort_t<256, 1>(c, W, n, idx, vals, ldi, s);
-    case 1: return launch_sort_t<256, 4>(c, W, n, idx, vals, ldi, s);
-    case 2: return launch_sort_t<512, 4>(c, W, n, idx, vals, ldi, s);
-    case 3: return launch_sort_t<1024, 4>(c, W, n, idx, vals, ldi, s);
-    case 4: return launch_sort_t<1024, 8>(c, W, n, idx, vals, ldi, s);
-    case 5: return launch_sort_t<1024, 12>(c, W, n, idx, vals, ldi, s);
-    case 6: return launch_sort_t<1024, 16>(c, W, n, idx, vals, ldi, s);
-    default: return launch_sort_t<1024, 20>(c, W, n, idx, vals, ldi, s);
+  const int cfg = kClassDefault[sort_class(n)];
+  switch (cfg) {
+#define X(i, b, t) \
+  case i: return launch_sort_t<b, t>(i, W, n, idx, vals, ldi, s);
+    TMFG_SORT_CFGS(X)
+#undef X
   }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace tmfg

@@ -99,3 +99,27 @@ def test_build_batch_plan_cache():
         assert code == 0
         torch.cuda.synchronize()
         assert [int(r.status.item()) for r in results] == [0, 0]
+
+
+def test_autotuned_batch_same_results():
+    """The tuner changes launch configurations only: results stay bitwise those of the
+    default batch, and the chosen configuration fits every size class present."""
+    inst = synth.config_c4(24)
+    dev = [("X", to_dev(s.X)) for s in inst]
+    ref = tm.Batch(dev)
+    want = [r.to_numpy() for r in ref.run()]
+    torch.cuda.synchronize()
+    tuned = tm.Batch(dev, flags=tm.BATCH_AUTOTUNE)
+    cfg = tuned.config()
+    assert cfg["tune_trials"] > 0 and cfg["loop_workgroups"] >= 1
+    assert any(c >= 0 for c in cfg["sort_config"])
+    for rep in range(2):
+        got = [r.to_numpy() for r in tuned.run()]
+        torch.cuda.synchronize()
+        for g, w in zip(got, want):
+            assert g["status"] == 0
+            same_tmfg(g, w)
+    base = ref.config()
+    assert base["tune_trials"] == 0
+    ref.close()
+    tuned.close()
