@@ -85,28 +85,49 @@ __device__ __forceinline__ void sort3(int& x, int& y, int& z) {
   if (x > y) { t = x; x = y; y = t; }
 }
 
-__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
-#pragma unroll
-  for (int off = kGroup / 2; off >= 1; off >>= 1) {
-    uint32_t lo = __shfl_xor((uint32_t)v, off, kWave);
-    uint32_t hi = __shfl_xor((uint32_t)(v >> 32), off, kWave);
-    uint64_t o = ((uint64_t)hi << 32) | lo;
-    v = o > v ? o : v;
-  }
-  return v;
+// Reductions inside a 16-lane row (one walk group) with DPP lane permutations, which run at
+// ALU latency instead of a trip through the LDS crossbar: pairs (quad_perm 1,0,3,2), quads
+// (quad_perm 2,3,0,1), half rows (row_half_mirror) and the whole row (row_mirror); every
+// lane of the row ends with the result. All lanes of the row must be active.
+constexpr int kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+static_assert(kGroup == 16, "a walk group is one DPP row");
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
 }
-__device__ __forceinline__ int group_incl_scan(int x, int gl) {
-#pragma unroll
-  for (int off = 1; off < kGroup; off <<= 1) {
-    const int y = __shfl_up(x, off, kGroup);
-    if (gl >= off) x += y;
-  }
-  return x;
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  return ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+  v = max64(v, dpp64<kDppXor1>(v));
+  v = max64(v, dpp64<kDppXor2>(v));
+  v = max64(v, dpp64<kDppHalfMirror>(v));
+  return max64(v, dpp64<kDppMirror>(v));
 }
 __device__ __forceinline__ int group_min_i32(int x) {
+  x = min(x, (int)dpp32<kDppXor1>((uint32_t)x));
+  x = min(x, (int)dpp32<kDppXor2>((uint32_t)x));
+  x = min(x, (int)dpp32<kDppHalfMirror>((uint32_t)x));
+  return min(x, (int)dpp32<kDppMirror>((uint32_t)x));
+}
+// Wave-wide maximum: row maxima by DPP, then the four rows read out lane by lane.
+__device__ __forceinline__ uint64_t wave_max_dpp(uint64_t v) {
+  v = group_max_u64(v);
+  uint64_t m = 0;
 #pragma unroll
-  for (int off = kGroup / 2; off >= 1; off >>= 1) x = min(x, __shfl_xor(x, off, kWave));
-  return x;
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 16 * r);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 16 * r);
+    m = max64(m, ((uint64_t)hi << 32) | lo);
+  }
+  return m;
 }
 
 // Threshold walk for one face by a group of kGroup lanes (gl = lane within the group,
@@ -665,7 +686,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           best = k > best ? k : best;
         }
       }
-      best = wave_max_u64(best);
+      best = wave_max_dpp(best);
       if (lane == 0) s_part[wave] = best;
       __syncthreads();
       if (tid == 0) {
@@ -686,7 +707,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       const int link = s_link[sl][lane];
       const uint4 crec = link >= 0 ? make_rec(work[link]) : s_crec[sl][lane];
       const uint64_t k = rec_key(crec);
-      const uint64_t mx = wave_max_u64(k);
+      const uint64_t mx = wave_max_dpp(k);
       const uint64_t msk = __ballot(k == mx);
       if (lane == (int)__builtin_ctzll(msk)) cmax[sel[sl]] = crec;
     }
@@ -704,8 +725,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         k1 = k > k1 ? k : k1;
         if (!is_ins(bits, rec_vertex(r))) kf = k > kf ? k : kf;
       }
-      k1 = wave_max_u64(k1);
-      kf = wave_max_u64(kf);
+      k1 = wave_max_dpp(k1);
+      kf = wave_max_dpp(kf);
       const int f1 = 0xffff - (int)((uint32_t)k1 >> 16);
       if (k1 != 0 && k1 == kf) {
         // Fresh maximum: insert its vertex.
@@ -753,7 +774,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
             const uint64_t k = rec_key(q);
             if (k && !is_ins(bits, rec_vertex(q))) kf2 = k > kf2 ? k : kf2;
           }
-          kf2 = wave_max_u64(kf2);
+          kf2 = wave_max_dpp(kf2);
           ns = select_stale_chunks(cmax, LL.nchunk, bits, kf2, sel, ns, lane);
         }
         if (lane == 0) {
