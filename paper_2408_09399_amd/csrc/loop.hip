@@ -481,7 +481,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ GroupBuf gbuf[kGroups];
   __shared__ uint4 s_crec[kMaxSel][kWave];       // the loaded chunk records
   __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
-  __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4];
+  __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
   __shared__ uint64_t s_floor;
   __shared__ uint64_t s_part[kWaves];
   __shared__ int s_vpart[kWaves];
@@ -574,6 +574,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     s_stop = 0;
     s_nsweep = 0;
     s_bmax = 0;
+    s_next = 0;
   }
   __syncthreads();
 
@@ -639,10 +640,16 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
     if (tid == 0) s_cnt[0] += nwork - nnew;
     const bool have_cand = s_ins < n;
-    // Phase B: best pair of every queued face, one group of kGroup lanes per face.
-    for (int base = 0; base < nwork; base += kGroups) {
-      if (tid == 0) s_cnt[4] += 1;
-      const int item = base + gid;
+    // Phase B: best pair of every queued face, one group of kGroup lanes per face. Each wave
+    // takes the next kWave / kGroup faces from a counter when it is free, so a deep walk
+    // holds up only its own wave.
+    for (;;) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(&s_next, kWave / kGroup);
+      base = __builtin_amdgcn_readfirstlane(base);
+      if (base >= nwork) break;
+      if (lane == 0) atomicAdd(&s_cnt[4], 1ull);
+      const int item = base + (lane / kGroup);
       if (item < nwork) {
         Work& w = work[item];
         uint64_t best = 0;
@@ -701,7 +708,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     TMFG_LAP(8);
     // Phase B3: publish the new face records. Phase C: rebuild the maxima of the loaded
     // chunks from the records held in registers, with the recomputed ones substituted.
-    if (tid == 0) s_nsweep = 0;
+    if (tid == 0) {
+      s_nsweep = 0;
+      s_next = 0;
+    }
     if (tid < nwork) P.frec[work[tid].f] = make_rec(work[tid]);
     for (int sl = wave; sl < nsel; sl += kWaves) {
       const int link = s_link[sl][lane];
