@@ -55,6 +55,9 @@ constexpr int kMaxWork = 256;                    // faces recomputed per selecti
 constexpr int kMaxSel = 48;                      // chunks loaded per selection phase
 constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
 static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
+// 64-face chunks of the largest build, and the chunk maxima each lane of a wave covers
+constexpr int kMaxChunks = (2 * kMaxN - 4 + 63) / 64;
+constexpr int kChunkIters = (kMaxChunks + kWave - 1) / kWave;
 // Time the sub-steps of one walk group (stats [16..19]); the waits it adds slow that group.
 constexpr bool kWalkDiag = false;
 
@@ -448,20 +451,18 @@ __device__ __forceinline__ uint4 make_rec(const Work& w) {
   return rec;
 }
 
-// Wave 0: append to sel[] every chunk whose maximum record is stale (vertex inserted) and
-// ranks above `floor`, other than the chunks already listed. Returns the new length.
-__device__ int select_stale_chunks(const uint4* cmax, int nchunk, const uint32_t* bits, uint64_t floor,
-                                   int* sel, int cnt, int lane) {
-  const int given = cnt;
-  for (int ch0 = 0; ch0 < nchunk; ch0 += kWave) {
-    const int ch = ch0 + lane;
-    bool pick = false;
-    if (ch < nchunk) {
-      const uint4 r = cmax[ch];
-      const uint64_t k = rec_key(r);
-      pick = k > floor && is_ins(bits, rec_vertex(r));
-      for (int q = 0; q < given; ++q) pick &= sel[q] != ch;
-    }
+// Wave 0: append to sel[] (after its first `cnt` entries) every chunk whose maximum record is
+// stale and ranks above `floor`, other than chunks c1 and c2 (already listed). The lane holds
+// the maxima of chunks lane + i * kWave (key words khi/klo, inserted flags in insm). Returns
+// the new length, at most kMaxSel.
+__device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uint32_t (&klo)[kChunkIters],
+                                   uint32_t insm, int nchunk, uint64_t floor, int c1, int c2, int* sel, int cnt,
+                                   int lane) {
+#pragma unroll
+  for (int i = 0; i < kChunkIters; ++i) {
+    const int ch = lane + i * kWave;
+    const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
+    const bool pick = ch < nchunk && ch != c1 && ch != c2 && k > floor && ((insm >> i) & 1u);
     const uint64_t msk = __ballot(pick);
     if (pick) {
       const int slot = cnt + (int)__popcll(msk & ((1ull << lane) - 1));
@@ -727,13 +728,27 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // Phase A: select (wave 0).
     if (tid == 0) s_cnt[3] += 1;
     if (wave == 0) {
+      // Every chunk maximum this lane covers is read once (all loads in flight together),
+      // then the inserted bits of their vertices; the top record, the best fresh one, the
+      // floor after an insertion and the stale chunks to reload all come from these.
+      uint32_t khi[kChunkIters], klo[kChunkIters];
+      uint32_t insm = 0;
+#pragma unroll
+      for (int i = 0; i < kChunkIters; ++i) {
+        const int ch = lane + i * kWave;
+        const uint4 r = cmax[ch < LL.nchunk ? ch : 0];
+        khi[i] = ch < LL.nchunk ? r.x : 0u;
+        klo[i] = ch < LL.nchunk ? r.y : 0u;
+      }
+#pragma unroll
+      for (int i = 0; i < kChunkIters; ++i)
+        insm |= is_ins(bits, (int)(klo[i] & 0xffffu)) ? (1u << i) : 0u;
       uint64_t k1 = 0, kf = 0;
-      for (int ch = lane; ch < LL.nchunk; ch += kWave) {
-        const uint4 r = cmax[ch];
-        const uint64_t k = rec_key(r);
-        if (!k) continue;
-        k1 = k > k1 ? k : k1;
-        if (!is_ins(bits, rec_vertex(r))) kf = k > kf ? k : kf;
+#pragma unroll
+      for (int i = 0; i < kChunkIters; ++i) {
+        const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
+        k1 = max64(k1, k);
+        kf = ((insm >> i) & 1u) ? kf : max64(kf, k);
       }
       k1 = wave_max_dpp(k1);
       kf = wave_max_dpp(kf);
@@ -744,8 +759,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         const int u = rec_vertex(r);
         const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
         const int F = s_F;
+        const int ins = s_ins;                 // vertices inserted before this one
         if (lane == 0) {
-          const int ins = s_ins, st = ins - 4;
+          const int st = ins - 4;
           P.order[ins] = u;
           int32_t* e = P.edges + 2 * (6 + 3 * st);
           e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
@@ -769,23 +785,25 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           sel[0] = f1 >> 6;
           sel[1] = F >> 6;       // F is even, so F and F + 1 share a chunk
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
         // The chunks of the three new faces are reloaded. Faces whose cached vertex was u
         // are stale now; the chunks whose maximum is stale and ranks above the best fresh
         // record that remains are loaded too, and every stale record in them ranked above
         // that floor is recomputed along with the new faces.
-        int ns = (F >> 6) != (f1 >> 6) ? 2 : 1;
+        const int c1 = f1 >> 6, c2 = F >> 6;
+        int ns = c2 != c1 ? 2 : 1;
         uint64_t kf2 = ~0ull;
-        if (s_ins < n) {
+        if (ins + 1 < n) {
+#pragma unroll
+          for (int i = 0; i < kChunkIters; ++i)
+            if ((klo[i] & 0xffffu) == (uint32_t)u) insm |= 1u << i;
           kf2 = 0;
-          for (int ch = lane; ch < LL.nchunk; ch += kWave) {
-            const uint4 q = cmax[ch];
-            const uint64_t k = rec_key(q);
-            if (k && !is_ins(bits, rec_vertex(q))) kf2 = k > kf2 ? k : kf2;
+#pragma unroll
+          for (int i = 0; i < kChunkIters; ++i) {
+            const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
+            kf2 = ((insm >> i) & 1u) ? kf2 : max64(kf2, k);
           }
           kf2 = wave_max_dpp(kf2);
-          ns = select_stale_chunks(cmax, LL.nchunk, bits, kf2, sel, ns, lane);
+          ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane);
         }
         if (lane == 0) {
           s_nsel = ns;
@@ -803,10 +821,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       } else {
         // Stale maximum: load every chunk whose maximum is stale and ranks above the best
         // fresh record (the top one first) and recompute their stale records above it.
-        if (lane == 0) sel[0] = f1 >> 6;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        const int ns = select_stale_chunks(cmax, LL.nchunk, bits, kf, sel, 1, lane);
+        const int c1 = f1 >> 6;
+        if (lane == 0) sel[0] = c1;
+        const int ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane);
         if (lane == 0) {
           s_nsel = ns;
           s_floor = kf;
