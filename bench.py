@@ -446,7 +446,8 @@ def main():
         "loop_stats": {"stale_recomputes": stats[0], "walk_rounds": stats[1], "sweeps": stats[2],
                        "phases": stats[3], "walk_batches": stats[4], "w_reads": stats[11],
                        "critical_rounds": stats[12], "walks_ge4": stats[13], "walks_ge16": stats[14],
-                       "skip_scans": stats[15],
+                       "skip_scans": stats[15], "stale_top_phases": stats[20],
+                       "work_overflow_phases": stats[21], "chunk_overflow_phases": stats[22],
                        "us": {"select": stats[5], "load": stats[6], "walk": stats[7],
                               "sweep": stats[8], "publish": stats[9], "kernel": stats[10]}},
         "roofline": roofline,

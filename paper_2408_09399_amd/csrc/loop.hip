@@ -55,6 +55,7 @@ constexpr int kMaxWork = 256;                    // faces recomputed per selecti
 constexpr int kMaxSel = 48;                      // chunks loaded per selection phase
 constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
 static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
+static_assert(kMaxWork <= kBlock, "one thread publishes each recomputed face");
 // 64-face chunks of the largest build, and the chunk maxima each lane of a wave covers
 constexpr int kMaxChunks = (2 * kMaxN - 4 + 63) / 64;
 constexpr int kChunkIters = (kMaxChunks + kWave - 1) / kWave;
@@ -583,11 +584,11 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   //   [0] stale recomputes [1] walk rounds [2] sweeps [3] phases [4] walk batches
   //   [5..9] ticks in select/load/walk/sweep/publish [11] W reads [12] critical rounds
   //   [13] walks >= 4 rounds [14] walks >= 16 rounds [15] skip scans
-  __shared__ unsigned long long s_cnt[16];
+  __shared__ unsigned long long s_cnt[19];
   __shared__ unsigned long long s_wt[4];         // walk sub-step ticks of group 0 (diagnostics)
   __shared__ int s_since_insert;
   __shared__ unsigned long long s_t0;
-  if (tid < 16) s_cnt[tid] = 0;
+  if (tid < 19) s_cnt[tid] = 0;
   if (tid < 4) s_wt[tid] = 0;
   if (tid == 0) {
     s_since_insert = 0;
@@ -639,7 +640,11 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     __syncthreads();
     TMFG_LAP(6);
     const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
-    if (tid == 0) s_cnt[0] += nwork - nnew;
+    if (tid == 0) {
+      s_cnt[0] += nwork - nnew;
+      if (s_nwork > kMaxWork) s_cnt[17] += 1;
+      if (nsel >= kMaxSel) s_cnt[18] += 1;
+    }
     const bool have_cand = s_ins < n;
     // Phase B: best pair of every queued face, one group of kGroup lanes per face. Each wave
     // takes the next kWave / kGroup faces from a counter when it is free, so a deep walk
@@ -822,6 +827,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         // Stale maximum: load every chunk whose maximum is stale and ranks above the best
         // fresh record (the top one first) and recompute their stale records above it.
         const int c1 = f1 >> 6;
+        if (lane == 0) s_cnt[16] += 1;
         if (lane == 0) sel[0] = c1;
         const int ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane);
         if (lane == 0) {
@@ -855,6 +861,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         P.stats[i] = (int32_t)(v > 0x7fffffffull ? 0x7fffffffull : v);
       }
       for (int i = 0; i < 4; ++i) P.stats[16 + i] = (int32_t)(s_wt[i] > 0x7fffffffull ? 0x7fffffffull : s_wt[i]);
+      for (int i = 0; i < 3; ++i) P.stats[20 + i] = (int32_t)(s_cnt[16 + i] > 0x7fffffffull ? 0x7fffffffull : s_cnt[16 + i]);
     }
   }
 }
