@@ -35,6 +35,10 @@ def parse():
     ap.add_argument("--config", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--batch", type=int, default=512, help="instances in the c4 batch")
     ap.add_argument("--requests", type=int, default=2200, help="c5: requests per replay (the first 200 warm up)")
+    ap.add_argument("--max-batch", type=int, default=512, help="c5: requests one server dispatch groups")
+    ap.add_argument("--streams", type=int, default=4, help="c5: server dispatches in flight")
+    ap.add_argument("--no-serial", action="store_true", help="c5: skip the serial plain-build comparison")
+    ap.add_argument("--fifo", action="store_true", help="c5: dispatch strictly in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1500)
     ap.add_argument("--calibration-copy", action="store_true",
@@ -313,8 +317,8 @@ def bench_serve(args):
     Xs = [r.series.X for r in trace]
     t_unit = np.array([r.t_arrival for r in trace])
     n_max = max(X.shape[0] for X in Xs)
-    srv = tm.Server(hbm_budget=96 << 30, host_budget=4 << 30, max_batch=512, n_streams=2,
-                    n_max=n_max, L_max=256)
+    srv = tm.Server(hbm_budget=96 << 30, host_budget=4 << 30, max_batch=args.max_batch, n_streams=args.streams,
+                    n_max=n_max, L_max=256, flags=tm.binding.SERVER_FIFO if args.fifo else 0)
     _replay(srv, Xs[: warm], t_unit, None, 0)                # first use: code paths, caches
     sat = _replay(srv, Xs, t_unit, None, 0)                  # everything at once
     rates = {}
@@ -327,6 +331,12 @@ def bench_serve(args):
 
     # serial plain builds of the same requests, one at a time in arrival order: service time
     # = copy in + build + copy out; latency from the single-server queue at each rate
+    if args.no_serial:
+        print(json.dumps({"metric": "p50/p99 latency at fixed QPS (request server, continuous batching)",
+                          "server": {"max_batch": args.max_batch, "n_streams": args.streams,
+                                     "policy": "fifo" if args.fifo else "size classes"},
+                          "saturated": sat, "at_rate": rates}))
+        return
     dev = torch.device("cuda:0")
     plan = tm.Plan(n_max, 256)
     service = np.empty(len(Xs))
@@ -353,7 +363,8 @@ def bench_serve(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"Poisson arrivals of {len(Xs)} rolling-window requests, n log-uniform in "
                                f"[100, 8000], L=256, from host memory", "requests": len(Xs),
-                   "server": {"max_batch": 512, "n_streams": 2}},
+                   "server": {"max_batch": args.max_batch, "n_streams": args.streams,
+                              "policy": "fifo" if args.fifo else "size classes"}},
         "saturated": sat, "at_rate": rates,
         "serial_plain": {"builds_per_s": round(len(Xs) / float(service.sum()), 1), "at_rate": serial},
     }

@@ -161,9 +161,9 @@ tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count
    (host_budget bytes), allocated at creation, and a scheduler thread. Requests wait in
    arrival order; each is admitted when its device footprint (input, scratch, results) and
    host footprint (staged input, results) fit in what is free. Whenever one of n_streams
-   stream slots is idle, every admitted request (up to max_batch) is dispatched there as
-   one grouped batch (the kernels of tmfg_batch_run, launched directly), so a new batch
-   starts while earlier ones still run. A request's results stay in the pinned region
+   stream slots is idle, admitted requests (up to max_batch, grouped by size class unless
+   TMFG_SERVER_FIFO) are dispatched there as one grouped batch (the kernels of
+   tmfg_batch_run, launched directly), so a new batch starts while earlier ones still run. A request's results stay in the pinned region
    until it is polled: requests that are never polled hold host memory and can stall
    admission. Every request gets the result tmfg_build gives it, bit for bit.
    submit, poll and stats may be called from any host thread. */
@@ -176,7 +176,15 @@ typedef struct {
   int32_t n_streams;      /* dispatches in flight at once (1..4) */
   int32_t n_max;          /* largest n accepted (4..20480) */
   int32_t L_max;          /* largest L accepted (>= 2) */
+  uint32_t flags;         /* TMFG_SERVER_FIFO, or 0 */
 } tmfg_server_config;
+
+/* Server flags. By default a dispatch takes the oldest waiting request and the waiting
+   requests of the same size class (n in [4, 256), [256, 1024), [1024, 4096), [4096, ...)),
+   so that small builds are not held up by the long serial chains of large ones; requests of
+   other classes keep their order for the next idle slot. TMFG_SERVER_FIFO dispatches
+   strictly in arrival order instead. */
+enum { TMFG_SERVER_FIFO = 1u << 0 };
 
 /* Result of one request, filled by tmfg_server_poll. The array pointers are HOST buffers
    given by the caller (sizes as in tmfg_job for this n), or NULL to skip that output. */

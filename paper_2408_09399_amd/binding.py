@@ -25,6 +25,7 @@ NO_VALIDATE = 1 << 0
 TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
 BATCH_AUTOTUNE = 1 << 3
+SERVER_FIFO = 1 << 0
 
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -76,7 +77,7 @@ class Job(ctypes.Structure):
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("host_budget", ctypes.c_size_t), ("max_batch", _I),
-                ("n_streams", _I), ("n_max", _I), ("L_max", _I)]
+                ("n_streams", _I), ("n_max", _I), ("L_max", _I), ("flags", ctypes.c_uint32)]
 
 
 class ServerResult(ctypes.Structure):
@@ -373,8 +374,8 @@ class Server:
     """
 
     def __init__(self, hbm_budget: int, host_budget: int, max_batch: int = 512, n_streams: int = 2,
-                 n_max: int = 8192, L_max: int = 1024):
-        cfg = ServerConfig(hbm_budget, host_budget, max_batch, n_streams, n_max, L_max)
+                 n_max: int = 8192, L_max: int = 1024, flags: int = 0):
+        cfg = ServerConfig(hbm_budget, host_budget, max_batch, n_streams, n_max, L_max, flags)
         h = ctypes.c_void_p()
         self._sizes = {}
         _check(_lib().tmfg_server_create(ctypes.byref(h), ctypes.cast(ctypes.pointer(cfg), ctypes.c_void_p)),

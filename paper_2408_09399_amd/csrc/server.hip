@@ -4,10 +4,12 @@
 // One scheduler thread owns the GPU side. Requests wait in arrival order; the head request
 // is admitted when its device footprint (input, scratch, results) and its pinned host
 // footprint (staged input, results) fit in the free ranges of two regions allocated once at
-// creation, so serving never calls the HIP allocator. Whenever a stream slot is idle, every
-// admitted request (up to max_batch) goes there as one batch: the grouped kernels of the
+// creation, so serving never calls the HIP allocator. Whenever a stream slot is idle, the
+// head request and the waiting requests of its size class (all waiting requests with
+// TMFG_SERVER_FIFO), up to max_batch, go there as one batch: the grouped kernels of the
 // batched form, launched directly, then one copy of each request's results to pinned
-// memory and an event. The scheduler polls the slots' events; a finished request frees its
+// memory and an event. A request completes with its batch, so grouping by size keeps small
+// builds from waiting for the long serial chains of large ones. The scheduler polls the slots' events; a finished request frees its
 // device range and its staged input at once, and its pinned results when the caller
 // collects them. Several slots let a new batch start while the long serial chains of an
 // earlier one still run.
@@ -35,6 +37,9 @@ namespace {
 constexpr int kMaxSlots = 4;
 constexpr int kMaxBatch = 4096;
 constexpr size_t kAlign = 256;
+
+// Size classes of the scheduler: n in [4, 256), [256, 1024), [1024, 4096), [4096, ...).
+int size_class(int n) { return n < 256 ? 0 : n < 1024 ? 1 : n < 4096 ? 2 : 3; }
 
 int64_t clock_ns() {
   return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
@@ -222,9 +227,16 @@ void scheduler(tmfg_server s) {
     for (int k = 0; k < s->nslots && !s->stop; ++k) {
       Slot& slot = s->slots[k];
       if (slot.busy || s->waiting.empty()) continue;
-      // admit from the head while both footprints fit
-      while (!s->waiting.empty() && (int)slot.reqs.size() < s->cfg.max_batch) {
-        Request* r = s->waiting.front();
+      // admit the oldest request, then (unless FIFO) later ones of its size class, while
+      // both footprints fit; the first one that does not fit ends the batch
+      const bool fifo = (s->cfg.flags & TMFG_SERVER_FIFO) != 0;
+      const int cls = size_class(s->waiting.front()->n);
+      for (auto it = s->waiting.begin(); it != s->waiting.end() && (int)slot.reqs.size() < s->cfg.max_batch;) {
+        Request* r = *it;
+        if (!fifo && size_class(r->n) != cls) {
+          ++it;
+          continue;
+        }
         size_t doff, hx, hr;
         if (!s->dev_alloc.alloc(r->dev_bytes, &doff)) break;
         if (!s->host_alloc.alloc(r->x_bytes, &hx)) {
@@ -240,7 +252,7 @@ void scheduler(tmfg_server s) {
         r->hx_off = hx;
         r->hr_off = hr;
         r->state = State::Running;
-        s->waiting.pop_front();
+        it = s->waiting.erase(it);
         slot.reqs.push_back(r);
       }
       if (slot.reqs.empty()) break;        // the head does not fit yet
@@ -291,7 +303,7 @@ tmfg_status tmfg_server_create(tmfg_server* out, const tmfg_server_config* cfg) 
   if (!out) return TMFG_E_INVALID;
   *out = nullptr;
   if (!cfg || cfg->hbm_budget == 0 || cfg->host_budget == 0 || cfg->max_batch < 1 || cfg->max_batch > kMaxBatch ||
-      cfg->n_streams < 1 || cfg->n_streams > kMaxSlots)
+      cfg->n_streams < 1 || cfg->n_streams > kMaxSlots || (cfg->flags & ~(uint32_t)TMFG_SERVER_FIFO))
     return TMFG_E_INVALID;
   if (cfg->n_max < tmfg::kMinN || cfg->n_max > tmfg::kMaxN || cfg->L_max < 2) return TMFG_E_SIZE;
   hipError_t e = tmfg::init_attributes_once();

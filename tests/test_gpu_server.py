@@ -38,9 +38,11 @@ def _serve(server, reqs):
     return [server.poll(t, wait_ms=-1) for t in tickets]
 
 
-def test_server_equals_solo_builds():
+@pytest.mark.parametrize("flags", [0, binding.SERVER_FIFO])
+def test_server_equals_solo_builds(flags):
     reqs = _requests(40, 3)
-    srv = tm.Server(hbm_budget=2 << 30, host_budget=256 << 20, max_batch=16, n_streams=2, n_max=2048, L_max=512)
+    srv = tm.Server(hbm_budget=2 << 30, host_budget=256 << 20, max_batch=16, n_streams=2, n_max=2048, L_max=512,
+                    flags=flags)
     got = _serve(srv, reqs)
     for X, g in zip(reqs, got):
         assert g["status"] == 0
