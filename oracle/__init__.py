@@ -15,6 +15,8 @@ Modules
                  as brute force over every pair, as a cached eager schedule and as a
                  lazy heap schedule (Section 4.2).
   invariants  -- structural checks on a finished TMFG.
+  paper_rule  -- the paper's candidate-limited rule with its heap schedule (Algorithm 2), as
+                 a heap and as batched recomputation with an ordered commit.
 
 Every function states the passage it follows and, where the paper is silent, the reading
 taken. Parity status of each function is listed in its docstring.
@@ -24,9 +26,11 @@ from .sortrows import sorted_row, sorted_rows
 from .tmfg import (seed_scores, seed_vertices, tmfg_exact, tmfg_lazy, tmfg_bruteforce,
                    face_best, SizeError)
 from .invariants import check_tmfg
+from .paper_rule import tmfg_paper, tmfg_paper_batched, check_paper_steps
 
 __all__ = [
     "pearson64", "DegenerateSeries", "NonFinite", "sorted_row", "sorted_rows",
     "seed_scores", "seed_vertices", "tmfg_exact", "tmfg_lazy", "tmfg_bruteforce",
+    "tmfg_paper", "tmfg_paper_batched", "check_paper_steps",
     "face_best", "SizeError", "check_tmfg",
 ]
