@@ -28,7 +28,7 @@ Two schedules compute the same result:
                       order in which the heap pops them, so the two agree; the GPU uses this
                       form.
 
-Pinned by: a hand-derived golden case (tests/golden/tmfg_paper_n7.json) on which the rule
+Pinned by: a hand-derived golden case (tests/golden/paper_rule_n7.json) on which the rule
 departs from the exact one; the structural invariants of oracle.invariants; the check that
 every inserted vertex is the first uninserted entry of one of its face's corners' sorted
 rows at the time of insertion (check_paper_steps); and the agreement of the two schedules

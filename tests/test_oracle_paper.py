@@ -11,7 +11,7 @@ from oracle import check_tmfg, tmfg_exact
 from oracle.paper_rule import check_paper_steps, tmfg_paper, tmfg_paper_batched
 from paper_2408_09399_amd import synth
 
-GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "tmfg_paper_n7.json")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_rule_n7.json")
 
 
 def _same(a, b):
