@@ -17,7 +17,8 @@
  *   - gain of face {a < b < c} and vertex u: float32 ((S[a][u] + S[b][u]) + S[c][u]);
  *   - each step takes the largest gain over all (live face, uninserted vertex) pairs; ties
  *     go to the lowest face id, then the lowest vertex id (this is the exact greedy rule of
- *     the sequential TMFG, Section 2; the paper's candidate heuristic is not used);
+ *     the sequential TMFG, Section 2). The paper's candidate rule (Algorithm 2) is
+ *     available with TMFG_RULE_PAPER;
  *   - the split face f = {x < y < z} with new vertex u keeps id f as sorted(u,x,y);
  *     sorted(u,y,z) and sorted(u,x,z) take the next two ids;
  *   - the per-vertex sort orders u != v by (S[v][u] desc, u asc), -0.0 equal to +0.0.
@@ -67,7 +68,16 @@ enum {
   TMFG_NO_VALIDATE = 1u << 0,   /* skip the finite / bitwise-symmetry check of a caller W */
   TMFG_TIMING = 1u << 1,        /* record per-phase HIP events (tmfg_plan_phase_ms) */
   TMFG_BATCH_NO_GRAPH = 1u << 2, /* batch: launch the kernels directly instead of a graph */
-  TMFG_BATCH_AUTOTUNE = 1u << 3  /* batch: pick launch configurations by timing them at creation */
+  TMFG_BATCH_AUTOTUNE = 1u << 3, /* batch: pick launch configurations by timing them at creation */
+  /* The paper's candidate-limited face rule and heap schedule (Sections 4.1 and 4.2,
+     Algorithm 2) instead of the exact greedy rule, for plans and batches. MaxCorrs[v] is
+     the most similar uninserted vertex of v (the first uninserted entry of v's sorted row),
+     evaluated when it is used; a face's pair is the MaxCorrs of its three corners with the
+     largest gain (ties to the lowest vertex id); pairs are taken by (gain desc, face id
+     asc), and a taken pair whose vertex is already inserted is recomputed and put back
+     before the next pair is taken. The result is the one that heap order gives, bit for
+     bit, not the exact greedy TMFG: its steps may take pairs of lower gain. */
+  TMFG_RULE_PAPER = 1u << 8
 };
 
 typedef struct tmfg_plan_s* tmfg_plan;
@@ -121,7 +131,10 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    spent loading and ranking list entries, reading candidate similarities, updating
    bounds, and skip-scanning (diagnostics), [20] selection phases that found a stale
    maximum, [21] phases with more stale faces than one phase recomputes, [22] phases that
-   loaded the most chunks one phase loads, [23..31] reserved. */
+   loaded the most chunks one phase loads, [23] recomputed pairs that were not committed
+   because a pair taken before them in heap order might change them (TMFG_RULE_PAPER),
+   [24..31] reserved. Under TMFG_RULE_PAPER, [1] counts scans for the first uninserted
+   entry of the corners' sorted rows instead of walk rounds. */
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
 
 /* ---- Batches: many independent builds in one graph replay ------------------------ */
@@ -131,7 +144,7 @@ tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
    phase as one grouped launch over all instances, and the insertion loops as one
    persistent launch whose workgroups take instances largest first. Each instance gets the
    result tmfg_build would give it, bit for bit. Flags: TMFG_NO_VALIDATE,
-   TMFG_BATCH_NO_GRAPH, TMFG_BATCH_AUTOTUNE. */
+   TMFG_BATCH_NO_GRAPH, TMFG_BATCH_AUTOTUNE, TMFG_RULE_PAPER. */
 tmfg_status tmfg_batch_create(tmfg_batch* batch, const tmfg_job* jobs, int32_t count, uint32_t flags);
 
 /* Run (replay) the batch on `stream`; the inputs may change between runs, the buffers may
@@ -176,15 +189,16 @@ typedef struct {
   int32_t n_streams;      /* dispatches in flight at once (1..4) */
   int32_t n_max;          /* largest n accepted (4..20480) */
   int32_t L_max;          /* largest L accepted (>= 2) */
-  uint32_t flags;         /* TMFG_SERVER_FIFO, or 0 */
+  uint32_t flags;         /* TMFG_SERVER_FIFO, TMFG_SERVER_RULE_PAPER, or 0 */
 } tmfg_server_config;
 
 /* Server flags. By default a dispatch takes the oldest waiting request and the waiting
    requests of the same size class (n in [4, 256), [256, 1024), [1024, 4096), [4096, ...)),
    so that small builds are not held up by the long serial chains of large ones; requests of
    other classes keep their order for the next idle slot. TMFG_SERVER_FIFO dispatches
-   strictly in arrival order instead. */
-enum { TMFG_SERVER_FIFO = 1u << 0 };
+   strictly in arrival order instead. TMFG_SERVER_RULE_PAPER builds every request with
+   the paper's face rule (as TMFG_RULE_PAPER does for a plan). */
+enum { TMFG_SERVER_FIFO = 1u << 0, TMFG_SERVER_RULE_PAPER = 1u << 1 };
 
 /* Result of one request, filled by tmfg_server_poll. The array pointers are HOST buffers
    given by the caller (sizes as in tmfg_job for this n), or NULL to skip that output. */

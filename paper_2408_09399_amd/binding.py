@@ -25,7 +25,9 @@ NO_VALIDATE = 1 << 0
 TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
 BATCH_AUTOTUNE = 1 << 3
+RULE_PAPER = 1 << 8
 SERVER_FIFO = 1 << 0
+SERVER_RULE_PAPER = 1 << 1
 
 # Every symbol the header declares, with its ctypes signature.
 _P = ctypes.c_void_p
@@ -236,8 +238,9 @@ def make_job(n: int, L: int, X, W, res: Result) -> Job:
 
 
 def build(X=None, W=None, plan: Optional[Plan] = None, stream=None, keep_w: bool = False,
-          out: Optional[Result] = None) -> Result:
-    """Enqueue one TMFG build (from series X (n, L) or similarity W (n, n), float32)."""
+          out: Optional[Result] = None, flags: int = 0) -> Result:
+    """Enqueue one TMFG build (from series X (n, L) or similarity W (n, n), float32).
+    `flags` are the plan flags (e.g. RULE_PAPER) of the plan made when none is given."""
     import torch
     if (X is None) == (W is None):
         raise ValueError("give exactly one of X and W")
@@ -245,7 +248,7 @@ def build(X=None, W=None, plan: Optional[Plan] = None, stream=None, keep_w: bool
     n = src.shape[0]
     L = src.shape[1] if X is not None else 0
     if plan is None:
-        plan = Plan(n, max(L, 2))
+        plan = Plan(n, max(L, 2), flags)
     res = out if out is not None else alloc_result(n, src.device, keep_w)
     job = make_job(n, L, X, W, res)
     _check(_lib().tmfg_build(plan.handle, ctypes.byref(job), _stream(stream)), "tmfg_build")

@@ -20,6 +20,7 @@ struct GroupList {
 
 struct BatchSpec {
   int count = 0, n_max = 0;
+  bool paper = false;                // every instance uses the paper's face rule
   std::vector<int> ints;             // every list, each padded to a multiple of 64 ints
   GroupList stdz, gemm, valid, seed, sort[8];
   size_t o_order = 0;                // job indices by n descending: the loop's queue order
@@ -59,6 +60,6 @@ hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipSt
 
 // Persistent loop grid for `count` jobs of largest size n_max: the loop workgroups that
 // fit on the device at once, at most one per job.
-hipError_t batch_grid(int device, int count, int n_max, int* grid);
+hipError_t batch_grid(int device, int count, int n_max, bool paper, int* grid);
 
 }  // namespace tmfg

@@ -370,6 +370,75 @@ __device__ bool walk_face(const LoopParams& P, const uint32_t* bits, uint16_t* p
   return done;
 }
 
+// The paper's pair of one face (Section 4.1, Algorithm 2), by a group of kGroup lanes: the
+// candidates are the MaxCorrs of the three corners, each the first uninserted entry of the
+// corner's sorted row, found from the corner's cached position kGroup * 8 entries at a time
+// (8 ids per lane, bitmap only); the pair is the candidate of largest gain, ties to the
+// lowest id (a vertex that is MaxCorrs of two corners is evaluated twice, to the same key).
+// Moves the corners' cached positions forward. 0 when no vertex is left.
+__device__ uint64_t paper_face(const LoopParams& P, const uint32_t* bits, uint16_t* ptr, int a, int b, int c,
+                               int gl, int* scans) {
+  const int n = P.n, m = n - 1;
+  const int ldi = (int)P.ldi;
+  const int x3[3] = {a, b, c};
+  int pos[3], cand[3];
+  bool open[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    // every entry before it is inserted; the group agrees on one value even if another
+    // group moves the position meanwhile
+    pos[t] = group_min_i32((int)ptr[x3[t]]);
+    cand[t] = -1;
+    open[t] = pos[t] < m;
+  }
+  int trips = 0;
+  while (open[0] || open[1] || open[2]) {
+    uint4 sv[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int qs = (pos[t] & ~7) + gl * 8;
+      sv[t] = *(const uint4*)(P.idx + (size_t)x3[t] * ldi + min(qs, ldi - 8));
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (!open[t]) continue;
+      const int qs = (pos[t] & ~7) + gl * 8;
+      const uint32_t wd[4] = {sv[t].x, sv[t].y, sv[t].z, sv[t].w};
+      int fp = 0x7fffffff;          // (position << 16) | id of the first uninserted entry
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const int p = qs + j;
+        const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
+        fp = ok ? min(fp, (p << 16) | u) : fp;
+      }
+      const int f = group_min_i32(fp);
+      if (f != 0x7fffffff) {
+        pos[t] = f >> 16;
+        cand[t] = f & 0xffff;
+        open[t] = false;
+      } else {
+        pos[t] = min((pos[t] & ~7) + kGroup * 8, m);
+        open[t] = pos[t] < m;
+      }
+    }
+    ++trips;
+  }
+  if (gl == 0) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (pos[t] > (int)ptr[x3[t]]) ptr[x3[t]] = (uint16_t)pos[t];
+  }
+  // lane t < 3 evaluates the candidate of corner t, all three similarities from W
+  const int t = gl < 3 ? gl : 0;
+  const int u = t == 0 ? cand[0] : t == 1 ? cand[1] : cand[2];
+  const int uc = u >= 0 ? u : 0;
+  const float wa = P.W[(size_t)a * n + uc], wb = P.W[(size_t)b * n + uc], wc = P.W[(size_t)c * n + uc];
+  const uint64_t k = (gl < 3 && u >= 0) ? cand_key((wa + wb) + wc, u) : 0;
+  *scans += trips;
+  return group_max_u64(k);
+}
+
 __device__ __forceinline__ uint64_t rec_key(const uint4& r) { return ((uint64_t)r.x << 32) | r.y; }
 __device__ __forceinline__ int rec_face(const uint4& r) { return 0xffff - (int)(r.y >> 16); }
 __device__ __forceinline__ int rec_vertex(const uint4& r) { return (int)(r.y & 0xffffu); }
@@ -455,10 +524,13 @@ __device__ __forceinline__ uint4 make_rec(const Work& w) {
 // Wave 0: append to sel[] (after its first `cnt` entries) every chunk whose maximum record is
 // stale and ranks above `floor`, other than chunks c1 and c2 (already listed). The lane holds
 // the maxima of chunks lane + i * kWave (key words khi/klo, inserted flags in insm). Returns
-// the new length, at most kMaxSel.
+// the new length, at most kMaxSel; with Dropped, *dropped receives the largest maximum of
+// the chunks left out for lack of room (0 if none), the same in every lane.
+template <bool Dropped>
 __device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uint32_t (&klo)[kChunkIters],
                                    uint32_t insm, int nchunk, uint64_t floor, int c1, int c2, int* sel, int cnt,
-                                   int lane) {
+                                   int lane, uint64_t* dropped) {
+  uint64_t dk = 0;
 #pragma unroll
   for (int i = 0; i < kChunkIters; ++i) {
     const int ch = lane + i * kWave;
@@ -468,15 +540,31 @@ __device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uin
     if (pick) {
       const int slot = cnt + (int)__popcll(msk & ((1ull << lane) - 1));
       if (slot < kMaxSel) sel[slot] = ch;
+      else if (Dropped) dk = max64(dk, k);
     }
     cnt += (int)__popcll(msk);
   }
+  if (Dropped) *dropped = wave_max_dpp(dk);
   return cnt < kMaxSel ? cnt : kMaxSel;
 }
+
+// The record a work item publishes, as one sortable key (0 when it has no vertex).
+__device__ __forceinline__ uint64_t work_key(const Work& w) { return rec_key(make_rec(w)); }
 
 __device__ __forceinline__ uint64_t clock_ticks() { return wall_clock64(); }
 }  // namespace
 
+// Paper selects the paper's face rule (Algorithm 2) in place of the exact one. Its cached
+// pairs are no upper bounds (a recomputed pair can rank higher than the one it replaces), so
+// the order of recomputation is part of the result: the heap pops stale pairs one at a time
+// in key order, and a pair made fresh at once competes with the next stale one. Each phase
+// recomputes in parallel the stale pairs ranked above the best fresh one, then commits a
+// recomputed pair only if its old key ranks above every fresh pair (those of the new faces
+// included), every recomputed pair of a stale record ranked above it, and every stale record
+// that was not recomputed; a pair not committed keeps its old record. This is the order in
+// which the heap would pop them. The top record of a phase that finds a stale maximum is
+// always recomputed and committed, so every such phase makes progress.
+template <bool Paper>
 __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ Work work[kMaxWork];
   __shared__ int sel[kMaxSel];
@@ -485,6 +573,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
   __shared__ uint64_t s_floor;
+  // paper rule: old keys and new keys of the work items, the best fresh record of the loaded
+  // chunks that stays, and the best stale record that was not recomputed
+  __shared__ uint64_t s_old[Paper ? kMaxWork : 1], s_newk[Paper ? kMaxWork : 1];
+  __shared__ uint64_t s_best0, s_unloaded;
   __shared__ uint64_t s_part[kWaves];
   __shared__ int s_vpart[kWaves];
 
@@ -577,18 +669,23 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     s_nsweep = 0;
     s_bmax = 0;
     s_next = 0;
+    if (Paper) {
+      s_best0 = 0;
+      s_unloaded = 0;
+    }
   }
   __syncthreads();
 
   // Counters (tmfg_plan_stats): kept in LDS so that they hold no registers in the loop.
   //   [0] stale recomputes [1] walk rounds [2] sweeps [3] phases [4] walk batches
   //   [5..9] ticks in select/load/walk/sweep/publish [11] W reads [12] critical rounds
-  //   [13] walks >= 4 rounds [14] walks >= 16 rounds [15] skip scans
-  __shared__ unsigned long long s_cnt[19];
+  //   [13] walks >= 4 rounds [14] walks >= 16 rounds [15] skip scans [16] stale maxima
+  //   [17] work overflows [18] chunk overflows [19] recomputed pairs not committed (paper)
+  __shared__ unsigned long long s_cnt[20];
   __shared__ unsigned long long s_wt[4];         // walk sub-step ticks of group 0 (diagnostics)
   __shared__ int s_since_insert;
   __shared__ unsigned long long s_t0;
-  if (tid < 19) s_cnt[tid] = 0;
+  if (tid < 20) s_cnt[tid] = 0;
   if (tid < 4) s_wt[tid] = 0;
   if (tid == 0) {
     s_since_insert = 0;
@@ -624,15 +721,25 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       int link = -1;
       for (int q = 0; q < nnew; ++q)
         if (work[q].f == f) link = q;
+      uint64_t kfresh = 0;
       if (link < 0 && s_ins < n) {
         const uint64_t k = rec_key(crec);
-        if (k != 0 && k > floor && is_ins(bits, rec_vertex(crec))) {
+        const bool stale = is_ins(bits, rec_vertex(crec));
+        if (k != 0 && k > floor && stale) {
           const int slot = atomicAdd(&s_nwork, 1);
           if (slot < kMaxWork) {
             work[slot] = Work{f, (int)(crec.z & 0xffffu), (int)(crec.z >> 16), (int)crec.w, 0, 0};
+            if (Paper) s_old[slot] = k;
             link = slot;
+          } else if (Paper) {
+            atomicMax(&s_unloaded, (unsigned long long)k);
           }
         }
+        if (Paper && !stale) kfresh = k;
+      }
+      if (Paper) {
+        kfresh = wave_max_dpp(kfresh);
+        if (lane == 0 && kfresh > s_best0) atomicMax(&s_best0, (unsigned long long)kfresh);
       }
       s_crec[sl][lane] = crec;
       s_link[sl][lane] = (int16_t)link;
@@ -661,9 +768,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         uint64_t best = 0;
         bool ok = true;
         int rw = 0, gw = 0, sw = 0;
-        if (have_cand)
-          ok = walk_face(P, bits, ptr, gbuf[gid], w.a, w.b, w.c, gl, gbase, best, &rw, &gw, &sw,
-                         (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
+        if (have_cand) {
+          if (Paper)
+            best = paper_face(P, bits, ptr, w.a, w.b, w.c, gl, &rw);
+          else
+            ok = walk_face(P, bits, ptr, gbuf[gid], w.a, w.b, w.c, gl, gbase, best, &rw, &gw, &sw,
+                           (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
+        }
         // per-lane W reads, summed over the group
         for (int off = kGroup / 2; off >= 1; off >>= 1) gw += __shfl_xor(gw, off, kWave);
         if (gl == 0) {
@@ -711,12 +822,33 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       }
       __syncthreads();
     }
+    if (Paper && nwork > nnew) {
+      // Ordered commit (paper rule): items [0, nnew) are always committed.
+      if (tid < nwork) s_newk[tid] = work_key(work[tid]);
+      __syncthreads();
+      if (tid >= nnew && tid < nwork) {
+        const uint64_t old = s_old[tid];
+        uint64_t lim = max64(max64(floor, s_best0), s_unloaded);
+        for (int q = 0; q < nnew; ++q) lim = max64(lim, s_newk[q]);
+        for (int q = nnew; q < nwork; ++q) lim = s_old[q] > old ? max64(lim, s_newk[q]) : lim;
+        if (old <= lim) {
+          // keep the old record: (gain, vertex) back into the item's pair
+          work[tid].best = (old & 0xffffffff00000000ull) | (0xffffull - (old & 0xffffull));
+          atomicAdd(&s_cnt[19], 1ull);
+        }
+      }
+      __syncthreads();
+    }
     TMFG_LAP(8);
     // Phase B3: publish the new face records. Phase C: rebuild the maxima of the loaded
     // chunks from the records held in registers, with the recomputed ones substituted.
     if (tid == 0) {
       s_nsweep = 0;
       s_next = 0;
+      if (Paper) {
+        s_best0 = 0;
+        s_unloaded = 0;
+      }
     }
     if (tid < nwork) P.frec[work[tid].f] = make_rec(work[tid]);
     for (int sl = wave; sl < nsel; sl += kWaves) {
@@ -808,7 +940,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
             kf2 = ((insm >> i) & 1u) ? kf2 : max64(kf2, k);
           }
           kf2 = wave_max_dpp(kf2);
-          ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane);
+          uint64_t dropped = 0;
+          ns = append_stale_chunks<Paper>(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane, &dropped);
+          if (Paper && lane == 0) s_unloaded = dropped;
         }
         if (lane == 0) {
           s_nsel = ns;
@@ -829,13 +963,23 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         const int c1 = f1 >> 6;
         if (lane == 0) s_cnt[16] += 1;
         if (lane == 0) sel[0] = c1;
-        const int ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane);
+        uint64_t dropped = 0;
+        const int ns = append_stale_chunks<Paper>(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane, &dropped);
         if (lane == 0) {
           s_nsel = ns;
           s_floor = kf;
           s_nwork = 0;
           s_nnew = 0;
           s_since_insert += 1;
+          if (Paper) {
+            // the top record is recomputed and committed first, whatever else fits
+            const uint4 r = cmax[c1];
+            work[0] = Work{f1, (int)(r.z & 0xffffu), (int)(r.z >> 16), (int)r.w, 0, 0};
+            s_nwork = 1;
+            s_nnew = 1;
+            s_cnt[0] += 1;
+            s_unloaded = dropped;
+          }
         }
       }
     }
@@ -861,19 +1005,21 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         P.stats[i] = (int32_t)(v > 0x7fffffffull ? 0x7fffffffull : v);
       }
       for (int i = 0; i < 4; ++i) P.stats[16 + i] = (int32_t)(s_wt[i] > 0x7fffffffull ? 0x7fffffffull : s_wt[i]);
-      for (int i = 0; i < 3; ++i) P.stats[20 + i] = (int32_t)(s_cnt[16 + i] > 0x7fffffffull ? 0x7fffffffull : s_cnt[16 + i]);
+      for (int i = 0; i < 4; ++i) P.stats[20 + i] = (int32_t)(s_cnt[16 + i] > 0x7fffffffull ? 0x7fffffffull : s_cnt[16 + i]);
     }
   }
 }
 
+template <bool Paper>
 __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  run_loop(P, smem);
+  run_loop<Paper>(P, smem);
 }
 
 // Batched form: persistent workgroups take instances, largest first, from a shared counter;
 // each runs that instance's whole insertion loop. The counter is read by one thread and
 // every workgroup ends when the list is used up.
+template <bool Paper>
 __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __restrict__ jobs,
                                                             const int* __restrict__ order, int count,
                                                             int* __restrict__ queue_head) {
@@ -902,19 +1048,22 @@ __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __re
     P.faces = J.faces;
     P.status = J.status;
     P.stats = nullptr;
-    run_loop(P, smem);
+    run_loop<Paper>(P, smem);
     __syncthreads();
   }
 }
 
 size_t loop_lds_bytes(int n) { return lds_layout(n).total; }
 
-hipError_t batch_loop_occupancy(int* per_cu, int n_max) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, batch_loop_kernel, kBlock, loop_lds_bytes(n_max));
+hipError_t batch_loop_occupancy(int* per_cu, int n_max, bool paper) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      per_cu, paper ? (const void*)batch_loop_kernel<true> : (const void*)batch_loop_kernel<false>, kBlock,
+      loop_lds_bytes(n_max));
 }
 
 hipError_t loop_init_attributes() {
-  const void* ks[2] = {(const void*)tmfg_loop_kernel, (const void*)batch_loop_kernel};
+  const void* ks[4] = {(const void*)tmfg_loop_kernel<false>, (const void*)tmfg_loop_kernel<true>,
+                       (const void*)batch_loop_kernel<false>, (const void*)batch_loop_kernel<true>};
   for (const void* k : ks) {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, k);
@@ -926,16 +1075,21 @@ hipError_t loop_init_attributes() {
 }
 
 hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
-                             int n_max, int32_t* stats, hipStream_t s) {
-  (void)stats;
+                             int n_max, bool paper, hipStream_t s) {
   const size_t lds = loop_lds_bytes(n_max);
-  hipLaunchKernelGGL(batch_loop_kernel, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
+  if (paper)
+    hipLaunchKernelGGL(batch_loop_kernel<true>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
+  else
+    hipLaunchKernelGGL(batch_loop_kernel<false>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
   return hipGetLastError();
 }
 
 hipError_t launch_loop(const LoopParams& p, hipStream_t s) {
   const size_t lds = loop_lds_bytes(p.n);
-  hipLaunchKernelGGL(tmfg_loop_kernel, dim3(1), dim3(kBlock), lds, s, p);
+  if (p.paper)
+    hipLaunchKernelGGL(tmfg_loop_kernel<true>, dim3(1), dim3(kBlock), lds, s, p);
+  else
+    hipLaunchKernelGGL(tmfg_loop_kernel<false>, dim3(1), dim3(kBlock), lds, s, p);
   return hipGetLastError();
 }
 

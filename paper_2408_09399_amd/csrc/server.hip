@@ -147,7 +147,7 @@ hipError_t dispatch(tmfg_server s, Slot& slot) {
     j.status = (int32_t*)(res + rl.status);
   }
   tmfg::BatchSpec spec;
-  if (tmfg::batch_describe(jobs.data(), count, 0, spec) != TMFG_OK || spec.ints.size() > s->ints_cap)
+  if (tmfg::batch_describe(jobs.data(), count, (s->cfg.flags & TMFG_SERVER_RULE_PAPER) ? TMFG_RULE_PAPER : 0u, spec) != TMFG_OK || spec.ints.size() > s->ints_cap)
     return hipErrorInvalidValue;
   tmfg::BatchJob* hj = (tmfg::BatchJob*)slot.h_desc;
   int* hi = (int*)(slot.h_desc + s->jobs_bytes);
@@ -161,7 +161,7 @@ hipError_t dispatch(tmfg_server s, Slot& slot) {
   L.d_ints = (const int*)(slot.d_desc + s->jobs_bytes);
   L.d_queue = (int*)(slot.d_desc + s->jobs_bytes + tmfg::align256(s->ints_cap * 4));
   hipError_t e;
-  if ((e = tmfg::batch_grid(s->device, count, spec.n_max, &L.grid)) != hipSuccess) return e;
+  if ((e = tmfg::batch_grid(s->device, count, spec.n_max, spec.paper, &L.grid)) != hipSuccess) return e;
   const hipStream_t st = slot.stream;
   if ((e = hipMemcpyAsync(L.d_jobs, hj, sizeof(tmfg::BatchJob) * count, hipMemcpyHostToDevice, st)) != hipSuccess)
     return e;
@@ -303,7 +303,7 @@ tmfg_status tmfg_server_create(tmfg_server* out, const tmfg_server_config* cfg) 
   if (!out) return TMFG_E_INVALID;
   *out = nullptr;
   if (!cfg || cfg->hbm_budget == 0 || cfg->host_budget == 0 || cfg->max_batch < 1 || cfg->max_batch > kMaxBatch ||
-      cfg->n_streams < 1 || cfg->n_streams > kMaxSlots || (cfg->flags & ~(uint32_t)TMFG_SERVER_FIFO))
+      cfg->n_streams < 1 || cfg->n_streams > kMaxSlots || (cfg->flags & ~(uint32_t)(TMFG_SERVER_FIFO | TMFG_SERVER_RULE_PAPER)))
     return TMFG_E_INVALID;
   if (cfg->n_max < tmfg::kMinN || cfg->n_max > tmfg::kMaxN || cfg->L_max < 2) return TMFG_E_SIZE;
   hipError_t e = tmfg::init_attributes_once();
