@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--fifo", action="store_true", help="c5: dispatch strictly in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1500)
+    ap.add_argument("--rule", default="exact", choices=["exact", "paper"],
+                    help="face rule: exact greedy, or the paper's candidate rule (Algorithm 2)")
+    ap.add_argument("--edge-sums", action="store_true",
+                    help="edge-sum study: exact vs paper face rule on the single-build workloads")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a 1 GiB device copy (the reference kernel for HBM counters)")
     return ap.parse_args()
@@ -218,16 +222,17 @@ def bench_batch(args):
             sys.exit(1)
         return wall
 
-    default = tm.Batch([("X", x) for x in Xs])
+    rule = tm.RULE_PAPER if args.rule == "paper" else 0
+    default = tm.Batch([("X", x) for x in Xs], flags=rule)
     wall_default = timed(default)
     default.close()
-    batch = tm.Batch([("X", x) for x in Xs], flags=tm.BATCH_AUTOTUNE)
+    batch = tm.Batch([("X", x) for x in Xs], flags=tm.BATCH_AUTOTUNE | rule)
     tuned_cfg = batch.config()
     wall = timed(batch)
     # the same instances, one build (one launch sequence) each, back to back on one plan
     n_max = max(s.X.shape[0] for s in inst)
     L_max = max(s.X.shape[1] for s in inst)
-    plan = tm.Plan(n_max, L_max)
+    plan = tm.Plan(n_max, L_max, rule)
     outs = [tm.alloc_result(x.shape[0], dev) for x in Xs]
     for x, o in zip(Xs[:8], outs[:8]):
         tm.build(X=x, plan=plan, out=o, stream=stream)
@@ -246,7 +251,7 @@ def bench_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(inst)} planted-cluster instances, n log-uniform in [64, 4096], "
                                f"L uniform in [64, 512]", "instances": len(inst),
-                   "sum_n": int(sum(s.X.shape[0] for s in inst))},
+                   "sum_n": int(sum(s.X.shape[0] for s in inst)), "rule": args.rule},
         "insertions_per_s": round(insertions / per, 1),
         "autotuned": tuned_cfg,
         "default_launch": {"ms_per_step": round(wall_default / args.steps * 1e3, 3),
@@ -318,7 +323,8 @@ def bench_serve(args):
     t_unit = np.array([r.t_arrival for r in trace])
     n_max = max(X.shape[0] for X in Xs)
     srv = tm.Server(hbm_budget=96 << 30, host_budget=4 << 30, max_batch=args.max_batch, n_streams=args.streams,
-                    n_max=n_max, L_max=256, flags=tm.binding.SERVER_FIFO if args.fifo else 0)
+                    n_max=n_max, L_max=256, flags=(tm.SERVER_FIFO if args.fifo else 0) |
+                    (tm.SERVER_RULE_PAPER if args.rule == "paper" else 0))
     _replay(srv, Xs[: warm], t_unit, None, 0)                # first use: code paths, caches
     sat = _replay(srv, Xs, t_unit, None, 0)                  # everything at once
     rates = {}
@@ -334,11 +340,11 @@ def bench_serve(args):
     if args.no_serial:
         print(json.dumps({"metric": "p50/p99 latency at fixed QPS (request server, continuous batching)",
                           "server": {"max_batch": args.max_batch, "n_streams": args.streams,
-                                     "policy": "fifo" if args.fifo else "size classes"},
+                                     "policy": "fifo" if args.fifo else "size classes"}, "rule": args.rule,
                           "saturated": sat, "at_rate": rates}))
         return
     dev = torch.device("cuda:0")
-    plan = tm.Plan(n_max, 256)
+    plan = tm.Plan(n_max, 256, tm.RULE_PAPER if args.rule == "paper" else 0)
     service = np.empty(len(Xs))
     for i, X in enumerate(Xs):
         t0 = time.perf_counter()
@@ -364,11 +370,75 @@ def bench_serve(args):
         "config": {"workload": f"Poisson arrivals of {len(Xs)} rolling-window requests, n log-uniform in "
                                f"[100, 8000], L=256, from host memory", "requests": len(Xs),
                    "server": {"max_batch": args.max_batch, "n_streams": args.streams,
-                              "policy": "fifo" if args.fifo else "size classes"}},
+                              "policy": "fifo" if args.fifo else "size classes"}, "rule": args.rule},
         "saturated": sat, "at_rate": rates,
         "serial_plain": {"builds_per_s": round(len(Xs) / float(service.sum()), 1), "at_rate": serial},
     }
     print(json.dumps(out))
+
+
+def edge_sum(W, edges) -> float:
+    """Sum of W over the TMFG's 3n-6 edges, in float64 (a quality diagnostic, Section 5.2)."""
+    import torch
+    e = edges.long()
+    return float(W[e[:, 0], e[:, 1]].double().sum().item())
+
+
+def rule_run(tm, X, steps, flags):
+    """Builds X with the given plan flags; returns (result, median loop ms, stats)."""
+    import torch
+    n, L = X.shape
+    plan = tm.Plan(n, L, tm.TIMING | flags)
+    res = tm.alloc_result(n, X.device, keep_w=True)
+    tm.build(X=X, plan=plan, out=res)
+    loops = []
+    for _ in range(steps):
+        tm.build(X=X, plan=plan, out=res)
+        loops.append(plan.phase_ms()[3])
+    torch.cuda.synchronize()
+    status = int(res.status.item())
+    if status != 0:
+        raise RuntimeError(f"build failed: {tm.STATUS.get(status)}")
+    stats = plan.stats()
+    plan.close()
+    return res, float(np.median(loops)), stats
+
+
+def paper_rule_summary(tm, X, res_exact, loop_ms_exact, steps) -> dict:
+    """The paper's face rule (Algorithm 2) on the same input: loop rate, counters, and its
+    edge sum against the exact rule's."""
+    n = X.shape[0]
+    res, loop_ms, st = rule_run(tm, X, steps, tm.RULE_PAPER)
+    es_p, es_e = edge_sum(res.W, res.edges), edge_sum(res_exact.W, res_exact.edges)
+    oe = res_exact.order.cpu().numpy()
+    op = res.order.cpu().numpy()
+    diff = np.flatnonzero(oe != op)
+    return {"loop_ms": round(loop_ms, 3), "loop_insertions_per_s": round((n - 4) / (loop_ms * 1e-3), 1),
+            "exact_loop_ms": round(loop_ms_exact, 3),
+            "edge_sum": round(es_p, 6), "exact_edge_sum": round(es_e, 6),
+            "edge_sum_rel_diff": float(f"{(es_p - es_e) / abs(es_e):.4e}"),
+            "first_order_difference": int(diff[0]) if diff.size else None,
+            "stats": {"stale_recomputes": st[0], "row_scans": st[1], "phases": st[3],
+                      "stale_top_phases": st[20], "work_overflow_phases": st[21],
+                      "chunk_overflow_phases": st[22], "not_committed": st[23]}}
+
+
+def bench_edge_sums(args):
+    """Edge-sum study (Section 5.2, Figure 7 analogue): exact greedy vs the paper's rule."""
+    import torch
+    import paper_2408_09399_amd as tm
+    rows = []
+    for name in ("c1", "c2", "c3"):
+        s = workload(name)
+        X = torch.from_numpy(s.X).to(torch.device("cuda:0"))
+        res_e, ms_e, _ = rule_run(tm, X, args.steps, 0)
+        row = paper_rule_summary(tm, X, res_e, ms_e, args.steps)
+        row["workload"] = f"{s.name}: n={s.X.shape[0]}, L={s.X.shape[1]}"
+        rows.append(row)
+        print(json.dumps(row), flush=True)
+        del X, res_e
+        torch.cuda.empty_cache()
+    print(json.dumps({"edge_sums": rows}))
 
 
 def main():
@@ -382,6 +452,8 @@ def main():
         return bench_batch(args)
     if args.config == "c5":
         return bench_serve(args)
+    if args.edge_sums:
+        return bench_edge_sums(args)
     import torch
     import paper_2408_09399_amd as tm
 
@@ -389,7 +461,7 @@ def main():
     n, L = s.X.shape
     dev = torch.device("cuda:0")
     X = torch.from_numpy(s.X).to(dev)
-    plan = tm.Plan(n, L, tm.TIMING)
+    plan = tm.Plan(n, L, tm.TIMING | (tm.RULE_PAPER if args.rule == "paper" else 0))
     res = tm.alloc_result(n, dev, keep_w=True)
     stream = torch.cuda.current_stream()
 
@@ -446,7 +518,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"single TMFG build from planted-cluster random-walk series, "
-                               f"n={n}, L={L} ({s.name})", "n": n, "L": L},
+                               f"n={n}, L={L} ({s.name})", "n": n, "L": L, "rule": args.rule},
         "phases_ms": {"similarity": round(ph[0], 3), "seed_scores": round(ph[1], 3),
                       "row_sort": round(ph[2], 3), "insertion_loop": round(ph[3], 3),
                       "total": round(ph[4], 3)},
@@ -464,7 +536,9 @@ def main():
         "roofline": roofline,
         "face_sweep_refresh": sweep_refresh(tm, plan, res.W, res, n, stream),
     }
-    if not args.no_cpu_baseline:
+    if args.rule == "exact":
+        out["paper_rule"] = paper_rule_summary(tm, X, res, float(ph[3]), min(args.steps, 3))
+    if not args.no_cpu_baseline and args.rule == "exact":
         out["cpu_baseline"] = cpu_baseline(s.X, res.W.cpu().numpy(), args.cpu_sample_steps)
     plan.close()
     print(json.dumps(out))

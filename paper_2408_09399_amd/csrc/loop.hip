@@ -524,13 +524,10 @@ __device__ __forceinline__ uint4 make_rec(const Work& w) {
 // Wave 0: append to sel[] (after its first `cnt` entries) every chunk whose maximum record is
 // stale and ranks above `floor`, other than chunks c1 and c2 (already listed). The lane holds
 // the maxima of chunks lane + i * kWave (key words khi/klo, inserted flags in insm). Returns
-// the new length, at most kMaxSel; with Dropped, *dropped receives the largest maximum of
-// the chunks left out for lack of room (0 if none), the same in every lane.
-template <bool Dropped>
+// the new length, at most kMaxSel.
 __device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uint32_t (&klo)[kChunkIters],
                                    uint32_t insm, int nchunk, uint64_t floor, int c1, int c2, int* sel, int cnt,
-                                   int lane, uint64_t* dropped) {
-  uint64_t dk = 0;
+                                   int lane) {
 #pragma unroll
   for (int i = 0; i < kChunkIters; ++i) {
     const int ch = lane + i * kWave;
@@ -540,13 +537,54 @@ __device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uin
     if (pick) {
       const int slot = cnt + (int)__popcll(msk & ((1ull << lane) - 1));
       if (slot < kMaxSel) sel[slot] = ch;
-      else if (Dropped) dk = max64(dk, k);
     }
     cnt += (int)__popcll(msk);
   }
-  if (Dropped) *dropped = wave_max_dpp(dk);
   return cnt < kMaxSel ? cnt : kMaxSel;
 }
+
+// Paper rule, wave 0: of the chunks whose maximum record is stale and ranks above `floor`
+// (other than c1 and c2), append to sel[] the kPaperChunks of highest maximum, in key order.
+// *rest receives the largest maximum of the others (0 if none), the same in every lane: no
+// record of an unlisted chunk ranks above it. Returns the new length.
+constexpr int kPaperChunks = 4;
+__device__ int pick_top_stale_chunks(const uint32_t (&khi)[kChunkIters], const uint32_t (&klo)[kChunkIters],
+                                     uint32_t insm, int nchunk, uint64_t floor, int c1, int c2, int* sel, int cnt,
+                                     int lane, uint64_t* rest) {
+  uint32_t cm = 0;                       // this lane's candidate chunks, by i
+#pragma unroll
+  for (int i = 0; i < kChunkIters; ++i) {
+    const int ch = lane + i * kWave;
+    const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
+    cm |= (ch < nchunk && ch != c1 && ch != c2 && k > floor && ((insm >> i) & 1u)) ? (1u << i) : 0u;
+  }
+  uint64_t lm = 0;                       // this lane's largest candidate and its index
+  int li = 0;
+  auto local_max = [&]() {
+    lm = 0;
+#pragma unroll
+    for (int i = 0; i < kChunkIters; ++i) {
+      const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
+      const bool c = ((cm >> i) & 1u) && k > lm;
+      lm = c ? k : lm;
+      li = c ? i : li;
+    }
+  };
+  local_max();
+  for (int s = 0; s < kPaperChunks; ++s) {
+    const uint64_t g = wave_max_dpp(lm);
+    if (g == 0) break;
+    if (lm == g) {                       // keys are unique: one lane holds it
+      sel[cnt] = lane + li * kWave;
+      cm &= ~(1u << li);
+      local_max();
+    }
+    ++cnt;
+  }
+  *rest = wave_max_dpp(lm);
+  return cnt;
+}
+static_assert(kPaperChunks + 2 <= kMaxSel, "the paper rule's chunks fit the load list");
 
 // The record a work item publishes, as one sortable key (0 when it has no vertex).
 __device__ __forceinline__ uint64_t work_key(const Work& w) { return rec_key(make_rec(w)); }
@@ -576,7 +614,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   // paper rule: old keys and new keys of the work items, the best fresh record of the loaded
   // chunks that stays, and the best stale record that was not recomputed
   __shared__ uint64_t s_old[Paper ? kMaxWork : 1], s_newk[Paper ? kMaxWork : 1];
-  __shared__ uint64_t s_best0, s_unloaded;
+  __shared__ uint64_t s_best0, s_unloaded, s_rest;
   __shared__ uint64_t s_part[kWaves];
   __shared__ int s_vpart[kWaves];
 
@@ -672,6 +710,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     if (Paper) {
       s_best0 = 0;
       s_unloaded = 0;
+      s_rest = 0;
     }
   }
   __syncthreads();
@@ -704,6 +743,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // stale record ranked above the floor, which is queued for recomputation.
     const int nsel = s_nsel, nnew = s_nnew;
     const uint64_t floor = s_floor;
+    // paper rule: stale records at or below the largest record of the chunks left unloaded
+    // cannot be committed this phase, so they are not recomputed
+    const uint64_t cut = Paper ? max64(floor, s_rest) : floor;
     // all of this wave's records are requested before any is used (one trip to memory)
     uint4 crecs[kSelPerWave];
 #pragma unroll
@@ -725,7 +767,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       if (link < 0 && s_ins < n) {
         const uint64_t k = rec_key(crec);
         const bool stale = is_ins(bits, rec_vertex(crec));
-        if (k != 0 && k > floor && stale) {
+        if (k != 0 && k > cut && stale) {
           const int slot = atomicAdd(&s_nwork, 1);
           if (slot < kMaxWork) {
             work[slot] = Work{f, (int)(crec.z & 0xffffu), (int)(crec.z >> 16), (int)crec.w, 0, 0};
@@ -848,6 +890,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
+        s_rest = 0;
       }
     }
     if (tid < nwork) P.frec[work[tid].f] = make_rec(work[tid]);
@@ -940,9 +983,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
             kf2 = ((insm >> i) & 1u) ? kf2 : max64(kf2, k);
           }
           kf2 = wave_max_dpp(kf2);
-          uint64_t dropped = 0;
-          ns = append_stale_chunks<Paper>(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane, &dropped);
-          if (Paper && lane == 0) s_unloaded = dropped;
+          if (Paper) {
+            uint64_t rest = 0;
+            ns = pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane, &rest);
+            if (lane == 0) s_unloaded = s_rest = rest;
+          } else {
+            ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane);
+          }
         }
         if (lane == 0) {
           s_nsel = ns;
@@ -963,8 +1010,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         const int c1 = f1 >> 6;
         if (lane == 0) s_cnt[16] += 1;
         if (lane == 0) sel[0] = c1;
-        uint64_t dropped = 0;
-        const int ns = append_stale_chunks<Paper>(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane, &dropped);
+        uint64_t rest = 0;
+        const int ns = Paper ? pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane, &rest)
+                             : append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane);
         if (lane == 0) {
           s_nsel = ns;
           s_floor = kf;
@@ -978,7 +1026,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
             s_nwork = 1;
             s_nnew = 1;
             s_cnt[0] += 1;
-            s_unloaded = dropped;
+            s_unloaded = s_rest = rest;
           }
         }
       }

@@ -1,5 +1,6 @@
 """The largest single-build workload (n=20000 series, L=1024) end to end: the full TMFG
-bit-exact against the lazy exact oracle fed the GPU's W bytes, plus invariants."""
+bit-exact against the lazy exact oracle fed the GPU's W bytes, plus invariants; and the
+same under the paper's face rule against its heap oracle."""
 import numpy as np
 import pytest
 import torch
@@ -22,5 +23,23 @@ def test_c3_full_parity():
     W = got["W"]
     print("c3: GPU build done, running the oracle", flush=True)
     ref = oracle.tmfg_lazy(W)
+    same_tmfg(got, ref)
+    oracle.check_tmfg(W, got, planarity=False)
+
+
+@pytest.mark.timeout(900)
+def test_c3_paper_rule_parity():
+    """The paper's face rule (Algorithm 2) at the same size, against the heap oracle."""
+    s = synth.config_c3()
+    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.RULE_PAPER)
+    res = tm.build(X=to_dev(s.X), keep_w=True, plan=plan)
+    torch.cuda.synchronize()
+    got = res.to_numpy()
+    assert got["status"] == 0
+    st = plan.stats()
+    print(f"c3 paper rule: stale recomputes {st[0]}, phases {st[3]}, not committed {st[23]}, "
+          f"work overflows {st[21]}, chunk overflows {st[22]}; running the oracle", flush=True)
+    W = got["W"]
+    ref = oracle.tmfg_paper(W)
     same_tmfg(got, ref)
     oracle.check_tmfg(W, got, planarity=False)
