@@ -17,6 +17,8 @@ Modules
   invariants  -- structural checks on a finished TMFG.
   paper_rule  -- the paper's candidate-limited rule with its heap schedule (Algorithm 2), as
                  a heap and as batched recomputation with an ordered commit.
+  corr_rule   -- the paper's correlation-based construction with a prefix size and eager
+                 updates (Algorithm 1).
 
 Every function states the passage it follows and, where the paper is silent, the reading
 taken. Parity status of each function is listed in its docstring.
@@ -27,10 +29,11 @@ from .tmfg import (seed_scores, seed_vertices, tmfg_exact, tmfg_lazy, tmfg_brute
                    face_best, SizeError)
 from .invariants import check_tmfg
 from .paper_rule import tmfg_paper, tmfg_paper_batched, check_paper_steps
+from .corr_rule import tmfg_corr, tmfg_corr_lazyrows
 
 __all__ = [
     "pearson64", "DegenerateSeries", "NonFinite", "sorted_row", "sorted_rows",
     "seed_scores", "seed_vertices", "tmfg_exact", "tmfg_lazy", "tmfg_bruteforce",
-    "tmfg_paper", "tmfg_paper_batched", "check_paper_steps",
+    "tmfg_paper", "tmfg_paper_batched", "check_paper_steps", "tmfg_corr", "tmfg_corr_lazyrows",
     "face_best", "SizeError", "check_tmfg",
 ]
