@@ -54,7 +54,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "paper_2408_09399_amd", "csrc")
 # source files whose text fixes each kernel's code; a traffic figure measured on other text is void
 KERNEL_SOURCES = {
-    "tmfg_loop": ["loop.hip", "common.h", "internal.h"],
+    "tmfg_loop": ["loop.hip", "facerule.h", "common.h", "internal.h"],
+    "tmfg_corr": ["corr.hip", "facerule.h", "common.h", "internal.h"],
     "corr_gemm": ["pearson.hip", "common.h", "internal.h"],
     "sort_rows": ["sort.hip", "common.h", "internal.h"],
 }

@@ -77,8 +77,19 @@ enum {
      asc), and a taken pair whose vertex is already inserted is recomputed and put back
      before the next pair is taken. The result is the one that heap order gives, bit for
      bit, not the exact greedy TMFG: its steps may take pairs of lower gain. */
-  TMFG_RULE_PAPER = 1u << 8
+  TMFG_RULE_PAPER = 1u << 8,
+  /* corr-tmfg (Section 4.1, Algorithm 1) with a prefix size p, 1 <= p <= 16, for plans and
+     batches: give TMFG_RULE_CORR_PREFIX(p). Faces hold pairs by the paper's candidate rule as
+     with TMFG_RULE_PAPER, but each round takes the p pairs of largest (gain, then lowest face
+     id), keeps for each vertex only the first of its pairs among them, applies the kept pairs
+     in that order (the k-th kept pair's split takes the next two face ids in turn), and then
+     recomputes, eagerly, every face whose pair vertex was inserted and every new face, against
+     the uninserted set after the whole round. Exclusive with TMFG_RULE_PAPER. */
+  TMFG_RULE_CORR = 1u << 9
 };
+#define TMFG_PREFIX_SHIFT 16
+#define TMFG_PREFIX_MASK (0xffu << TMFG_PREFIX_SHIFT)
+#define TMFG_RULE_CORR_PREFIX(p) (TMFG_RULE_CORR | ((uint32_t)(p) << TMFG_PREFIX_SHIFT))
 
 typedef struct tmfg_plan_s* tmfg_plan;
 typedef struct tmfg_batch_s* tmfg_batch;
@@ -134,7 +145,10 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    loaded the most chunks one phase loads, [23] recomputed pairs that were not committed
    because a pair taken before them in heap order might change them (TMFG_RULE_PAPER),
    [24..31] reserved. Under TMFG_RULE_PAPER, [1] counts scans for the first uninserted
-   entry of the corners' sorted rows instead of walk rounds. */
+   entry of the corners' sorted rows instead of walk rounds. Under TMFG_RULE_CORR only these
+   are kept: [0] faces recomputed because their pair vertex was inserted, [1] row scans,
+   [2] extra passes (a round with more faces to recompute than one pass takes), [3] rounds,
+   [10] microseconds of the kernel; the others read 0. */
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
 
 /* ---- Batches: many independent builds in one graph replay ------------------------ */
@@ -144,7 +158,7 @@ tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
    phase as one grouped launch over all instances, and the insertion loops as one
    persistent launch whose workgroups take instances largest first. Each instance gets the
    result tmfg_build would give it, bit for bit. Flags: TMFG_NO_VALIDATE,
-   TMFG_BATCH_NO_GRAPH, TMFG_BATCH_AUTOTUNE, TMFG_RULE_PAPER. */
+   TMFG_BATCH_NO_GRAPH, TMFG_BATCH_AUTOTUNE, TMFG_RULE_PAPER, TMFG_RULE_CORR_PREFIX(p). */
 tmfg_status tmfg_batch_create(tmfg_batch* batch, const tmfg_job* jobs, int32_t count, uint32_t flags);
 
 /* Run (replay) the batch on `stream`; the inputs may change between runs, the buffers may

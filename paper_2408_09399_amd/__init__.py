@@ -6,8 +6,8 @@ generators. The library is loaded on first use, and a missing build raises.
 """
 from .binding import (Plan, Result, Batch, Server, TmfgError, build, correlation, sort_rows, seed, face_sweep,
                       footprint_bytes, alloc_result, STATUS, NO_VALIDATE, TIMING, BATCH_NO_GRAPH, BATCH_AUTOTUNE,
-                      RULE_PAPER, SERVER_FIFO, SERVER_RULE_PAPER, PENDING)
+                      RULE_PAPER, RULE_CORR, rule_corr_prefix, SERVER_FIFO, SERVER_RULE_PAPER, PENDING)
 
 __all__ = ["Plan", "Result", "Batch", "Server", "TmfgError", "build", "correlation", "sort_rows", "seed",
            "face_sweep", "footprint_bytes", "alloc_result", "STATUS", "NO_VALIDATE", "TIMING",
-           "BATCH_NO_GRAPH", "BATCH_AUTOTUNE", "RULE_PAPER", "SERVER_FIFO", "SERVER_RULE_PAPER", "PENDING"]
+           "BATCH_NO_GRAPH", "BATCH_AUTOTUNE", "RULE_PAPER", "RULE_CORR", "rule_corr_prefix", "SERVER_FIFO", "SERVER_RULE_PAPER", "PENDING"]

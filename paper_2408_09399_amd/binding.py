@@ -26,6 +26,15 @@ TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
 BATCH_AUTOTUNE = 1 << 3
 RULE_PAPER = 1 << 8
+RULE_CORR = 1 << 9
+PREFIX_SHIFT = 16
+
+
+def rule_corr_prefix(p: int) -> int:
+    """Plan/batch flags for corr-tmfg (Algorithm 1) with prefix size p (1..16)."""
+    return RULE_CORR | (int(p) << PREFIX_SHIFT)
+
+
 SERVER_FIFO = 1 << 0
 SERVER_RULE_PAPER = 1 << 1
 

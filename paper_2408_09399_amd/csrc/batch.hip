@@ -39,6 +39,7 @@ hipError_t init_attributes_once() {
   std::call_once(once, [] {
     err = sort_init_attributes();
     if (err == hipSuccess) err = loop_init_attributes();
+    if (err == hipSuccess) err = corr_init_attributes();
   });
   return err;
 }
@@ -72,7 +73,7 @@ size_t batch_ints_capacity(int count) { return (size_t)10 * count + 12 + 24 * 64
 tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, BatchSpec& spec) {
   spec = BatchSpec();
   spec.count = count;
-  spec.paper = (flags & TMFG_RULE_PAPER) != 0;
+  if (!rule_from_flags(flags, &spec.paper, &spec.prefix)) return TMFG_E_INVALID;
   spec.scratch.resize(count);
   for (int i = 0; i < count; ++i) {
     const tmfg_status st = job_scratch_bytes(jobs[i], &spec.scratch[i]);
@@ -187,6 +188,8 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
     return e;
   for (int c = 0; c < kSortClasses; ++c)
     if ((e = batch_enqueue_sort(spec, L, c, s)) != hipSuccess) return e;
+  if (spec.prefix > 0)
+    return launch_batch_corr(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.prefix, s);
   return launch_batch_loop(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper, s);
 }
 
@@ -201,14 +204,19 @@ hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipSt
   hipError_t e;
   // the queue only: error flags raised by the earlier phases stay, and stop their instances
   if ((e = launch_batch_reset(L.d_jobs, spec.count, L.d_queue, false, s)) != hipSuccess) return e;
+  if (spec.prefix > 0)
+    return launch_batch_corr(L.d_jobs, L.d_ints + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max,
+                             spec.prefix, s);
   return launch_batch_loop(L.d_jobs, L.d_ints + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper, s);
 }
 
-hipError_t batch_grid(int device, int count, int n_max, bool paper, int* grid) {
+hipError_t batch_grid(int device, int count, int n_max, bool paper, int prefix, int* grid) {
   int cus = 0, per_cu = 0;
   hipError_t e;
   if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess) return e;
-  if ((e = batch_loop_occupancy(&per_cu, n_max, paper)) != hipSuccess) return e;
+  if ((e = prefix > 0 ? batch_corr_occupancy(&per_cu, n_max) : batch_loop_occupancy(&per_cu, n_max, paper)) !=
+      hipSuccess)
+    return e;
   *grid = std::max(1, std::min(count, cus * std::max(per_cu, 1)));
   return hipSuccess;
 }
@@ -366,7 +374,7 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
   if (!out) return TMFG_E_INVALID;
   *out = nullptr;
   if (!jobs || count <= 0) return TMFG_E_INVALID;
-  if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_BATCH_NO_GRAPH | TMFG_BATCH_AUTOTUNE | TMFG_RULE_PAPER))
+  if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_BATCH_NO_GRAPH | TMFG_BATCH_AUTOTUNE | tmfg::kRuleFlags))
     return TMFG_E_INVALID;
   tmfg::BatchSpec spec;
   const tmfg_status st = tmfg::batch_describe(jobs, count, flags, spec);
@@ -412,7 +420,7 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
   }
   if ((e = hipMemcpy(L.d_jobs, hj.data(), sizeof(tmfg::BatchJob) * count, hipMemcpyHostToDevice)) != hipSuccess ||
       (e = hipMemcpy(d_ints, b->spec.ints.data(), b->spec.ints.size() * 4, hipMemcpyHostToDevice)) != hipSuccess ||
-      (e = tmfg::batch_grid(b->device, count, b->spec.n_max, b->spec.paper, &L.grid)) != hipSuccess) {
+      (e = tmfg::batch_grid(b->device, count, b->spec.n_max, b->spec.paper, b->spec.prefix, &L.grid)) != hipSuccess) {
     batch_free(b);
     return fail(e);
   }

@@ -21,6 +21,7 @@ struct GroupList {
 struct BatchSpec {
   int count = 0, n_max = 0;
   bool paper = false;                // every instance uses the paper's face rule
+  int prefix = 0;                    // > 0: every instance uses corr-tmfg with this prefix
   std::vector<int> ints;             // every list, each padded to a multiple of 64 ints
   GroupList stdz, gemm, valid, seed, sort[8];
   size_t o_order = 0;                // job indices by n descending: the loop's queue order
@@ -60,6 +61,19 @@ hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipSt
 
 // Persistent loop grid for `count` jobs of largest size n_max: the loop workgroups that
 // fit on the device at once, at most one per job.
-hipError_t batch_grid(int device, int count, int n_max, bool paper, int* grid);
+hipError_t batch_grid(int device, int count, int n_max, bool paper, int prefix, int* grid);
+
+// The face rule that plan or batch flags select: false when they name an unknown rule, both
+// rules, or a corr-tmfg prefix outside [1, kMaxPrefix] (or a prefix without that rule).
+inline bool rule_from_flags(uint32_t flags, bool* paper, int* prefix) {
+  const bool corr = (flags & TMFG_RULE_CORR) != 0;
+  const int p = (int)((flags & TMFG_PREFIX_MASK) >> TMFG_PREFIX_SHIFT);
+  *paper = (flags & TMFG_RULE_PAPER) != 0;
+  *prefix = corr ? p : 0;
+  if (corr) return !*paper && p >= 1 && p <= kMaxPrefix;
+  return p == 0;
+}
+// Flag bits that select the face rule.
+constexpr uint32_t kRuleFlags = TMFG_RULE_PAPER | TMFG_RULE_CORR | TMFG_PREFIX_MASK;
 
 }  // namespace tmfg

@@ -2,6 +2,7 @@
 #include "../../include/tmfg.h"
 #include "common.h"
 #include "internal.h"
+#include "batchplan.h"
 
 #include <new>
 
@@ -149,7 +150,11 @@ size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags) {
 tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags) {
   if (!plan) return TMFG_E_INVALID;
   *plan = nullptr;
-  if (flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING | TMFG_RULE_PAPER)) return TMFG_E_INVALID;
+  bool paper = false;
+  int prefix = 0;
+  if ((flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING | tmfg::kRuleFlags)) ||
+      !tmfg::rule_from_flags(flags, &paper, &prefix))
+    return TMFG_E_INVALID;
   if (n_max < tmfg::kMinN || n_max > tmfg::kMaxN || L_max < 2) return TMFG_E_SIZE;
   hipError_t e = tmfg::init_attributes_once();
   if (e != hipSuccess) return hip_fail(e);
@@ -244,8 +249,8 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
   P.faces = job->faces;
   P.status = job->status;
   P.stats = plan->stats;
-  P.paper = (plan->flags & TMFG_RULE_PAPER) != 0;
-  TMFG_HIP(tmfg::launch_loop(P, stream));
+  tmfg::rule_from_flags(plan->flags, &P.paper, &P.prefix);
+  TMFG_HIP(P.prefix > 0 ? tmfg::launch_corr(P, stream) : tmfg::launch_loop(P, stream));
   record(plan, 4, stream);
   plan->timed = (plan->flags & TMFG_TIMING) != 0;
   return TMFG_OK;
@@ -259,7 +264,7 @@ tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count
       plan->batch = nullptr;
     }
     const tmfg_status st =
-        tmfg_batch_create(&plan->batch, jobs, count, plan->flags & (TMFG_NO_VALIDATE | TMFG_RULE_PAPER));
+        tmfg_batch_create(&plan->batch, jobs, count, plan->flags & (TMFG_NO_VALIDATE | tmfg::kRuleFlags));
     if (st != TMFG_OK) return st;
   }
   return tmfg_batch_run(plan->batch, stream);

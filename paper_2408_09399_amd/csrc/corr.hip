@@ -1,0 +1,452 @@
+// corr-tmfg with a prefix size (Section 4.1, Algorithm 1): one persistent workgroup runs the
+// rounds of one build on the device.
+//
+// Every face holds one pair: the best, by gain, of the MaxCorrs of its three corners (the
+// first uninserted entry of each corner's sorted row). A round takes the p pairs of largest
+// (gain, then lowest face id), keeps for each vertex only the first of its pairs among them,
+// and applies the kept pairs in that order (three edges each, the face split in three, the
+// new faces taking the next ids in turn). Then every face whose pair vertex was just inserted
+// and every new face gets its pair again: the update is eager, so after a round no pair
+// names an inserted vertex, and the order in which the pairs are recomputed does not matter.
+// That makes a round's recomputations independent of each other, unlike the heap schedule
+// of Algorithm 2, whose recomputations form a chain.
+//
+// Layout. Face records (16 B, the same format as the lazy loop's) live in global memory; in
+// LDS sit the inserted bitmap, the per-vertex first-uninserted positions, the maximum key of
+// every 64-face chunk, and the pair vertex of every face (0xffff: none, or being rebuilt).
+// One round:
+//   A  wave 0 takes the p chunks of largest maximum (the p best pairs lie in them), loads
+//      their keys, picks the p best, drops repeated vertices, reads the kept faces' corners
+//      and applies them; the new faces become work items;
+//   S  every face whose pair vertex is inserted is found by a scan of the pair vertices and
+//      becomes a work item (at most one per thread; more wait for another pass);
+//   B  each work item's pair, one group of 16 lanes per face;
+//   P  records and pair vertices are published; the chunks they touch are marked;
+//   R  the maxima of the touched chunks are rebuilt from their records.
+#include "common.h"
+#include "facerule.h"
+#include "internal.h"
+
+namespace tmfg {
+
+namespace {
+constexpr int cBlock = 512;
+constexpr int cWaves = cBlock / kWave;
+constexpr int cMaxWork = cBlock;                 // faces recomputed per pass, one per thread
+constexpr int cMaxChunks = (2 * kMaxN - 4 + 63) / 64;
+constexpr int cChunkIters = (cMaxChunks + kWave - 1) / kWave;
+constexpr uint16_t kNoVertex = 0xffff;
+static_assert(kMaxPrefix <= kWave, "the prefix fits one wave's selection");
+
+struct CorrLds {
+  int nchunk;
+  size_t off_ckey, off_bits, off_ptr, off_fvert, total;
+};
+__host__ __device__ inline CorrLds corr_layout(int n) {
+  CorrLds L;
+  const int nf = 2 * n - 4;
+  L.nchunk = (nf + 63) / 64;
+  auto r16 = [](size_t b) { return (b + 15) / 16 * 16; };         // every array 16-byte aligned
+  L.off_ckey = 0;                                                  // uint64[nchunk]
+  L.off_bits = L.off_ckey + r16((size_t)L.nchunk * 8);             // uint32[(n + 31) / 32]
+  L.off_ptr = L.off_bits + r16((size_t)((n + 31) / 32) * 4);       // uint16[n]
+  L.off_fvert = L.off_ptr + r16((size_t)n * 2);                    // uint16[nf], padded to 8
+  L.total = L.off_fvert + r16((size_t)nf * 2);
+  return L;
+}
+
+struct CWork {
+  int f, a, b, c;
+  uint64_t best;
+};
+}  // namespace
+
+__device__ void run_corr(const LoopParams& P, uint8_t* smem) {
+  __shared__ CWork work[cMaxWork];
+  __shared__ uint4 s_lrec[kMaxPrefix];             // records of the round's kept pairs, in order
+  __shared__ int s_sel[kMaxPrefix];
+  __shared__ uint32_t s_touch[(cMaxChunks + 31) / 32];
+  __shared__ int s_tlist[cMaxChunks];
+  __shared__ int s_nwork, s_listed, s_more, s_ins, s_F, s_stop, s_next, s_ntouch, s_seed[4];
+  __shared__ uint64_t s_part[cWaves];
+  __shared__ int s_vpart[cWaves];
+  // counters: [0] stale recomputes [1] row-scan trips [2] extra passes [3] rounds
+  __shared__ unsigned long long s_cnt[4];
+
+  const int n = P.n, p = P.prefix;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int gl = lane & (kGroup - 1);
+  const CorrLds LL = corr_layout(n);
+  uint64_t* ckey = (uint64_t*)(smem + LL.off_ckey);
+  uint32_t* bits = (uint32_t*)(smem + LL.off_bits);
+  uint16_t* ptr = (uint16_t*)(smem + LL.off_ptr);
+  uint16_t* fvert = (uint16_t*)(smem + LL.off_fvert);
+  const int nf = 2 * n - 4;
+  const int nw = (n + 31) / 32;
+  const uint64_t t_start = wall_clock64();
+
+  const uint32_t fl = *P.flags;
+  if (fl) {
+    if (tid == 0) {
+      *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+    }
+    return;
+  }
+
+  for (int i = tid; i < nf; i += cBlock) P.frec[i] = make_uint4(0, 0, 0, 0);
+  for (int i = tid; i < LL.nchunk; i += cBlock) ckey[i] = 0;
+  for (int i = tid; i < nw; i += cBlock) bits[i] = 0;
+  for (int i = tid; i < n; i += cBlock) ptr[i] = 0;
+  for (int i = tid; i < (int)((LL.total - LL.off_fvert) / 2); i += cBlock) fvert[i] = kNoVertex;
+  for (int i = tid; i < (cMaxChunks + 31) / 32; i += cBlock) s_touch[i] = 0;
+  if (tid < 4) s_cnt[tid] = 0;
+
+  seed_top4<cBlock>(P.scores, n, s_seed, s_part, s_vpart);
+  if (tid == 0) {
+    const int v1 = s_seed[0], v2 = s_seed[1], v3 = s_seed[2], v4 = s_seed[3];
+    P.order[0] = v1; P.order[1] = v2; P.order[2] = v3; P.order[3] = v4;
+    const int e[12] = {v1, v2, v1, v3, v1, v4, v2, v3, v2, v4, v3, v4};
+    for (int i = 0; i < 12; ++i) P.edges[i] = e[i];
+    for (int q = 0; q < 4; ++q) bits[s_seed[q] >> 5] |= 1u << (s_seed[q] & 31);
+    const int tri[4][3] = {{v1, v2, v3}, {v1, v2, v4}, {v1, v3, v4}, {v2, v3, v4}};
+    for (int f = 0; f < 4; ++f) {
+      int x = tri[f][0], y = tri[f][1], z = tri[f][2];
+      sort3(x, y, z);
+      work[f] = CWork{f, x, y, z, 0};
+    }
+    s_nwork = 4;
+    s_listed = 4;
+    s_ins = 4;
+    s_F = 4;
+    s_stop = 0;
+    s_more = 0;
+    s_next = 0;
+  }
+  __syncthreads();
+
+  for (;;) {
+    const bool have_cand = s_ins < n;
+    // ---- passes: the listed faces and every face whose pair vertex is inserted
+    for (int pass = 0;; ++pass) {
+      if (have_cand) {
+        // S: pair vertices, eight per 16-byte read; the matching faces' corners come from
+        // their records
+        const int F = s_F;
+        for (int q = tid; q * 8 < F; q += cBlock) {
+          const uint4 v8 = *(const uint4*)(fvert + 8 * q);
+          const uint32_t wd[4] = {v8.x, v8.y, v8.z, v8.w};
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const int f = 8 * q + j;
+            const int v = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+            if (f < F && v != kNoVertex && is_ins(bits, v)) {
+              const int slot = atomicAdd(&s_nwork, 1);
+              if (slot < cMaxWork) {
+                const uint4 r = P.frec[f];
+                work[slot] = CWork{f, (int)(r.z & 0xffffu), (int)(r.z >> 16), (int)r.w, 0};
+              } else {
+                s_more = 1;
+              }
+            }
+          }
+        }
+        __syncthreads();
+        if (tid == 0) s_cnt[0] += (unsigned long long)((s_nwork < cMaxWork ? s_nwork : cMaxWork) - s_listed);
+      }
+      const int nwork = s_nwork < cMaxWork ? s_nwork : cMaxWork;
+      // B: the pair of every listed face
+      for (;;) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_next, kWave / kGroup);
+        base = __builtin_amdgcn_readfirstlane(base);
+        if (base >= nwork) break;
+        const int item = base + (lane / kGroup);
+        if (item < nwork) {
+          CWork& w = work[item];
+          int trips = 0;
+          const uint64_t best =
+              have_cand ? paper_face(P.W, P.idx, n, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
+          if (gl == 0) {
+            w.best = best;
+            atomicAdd(&s_cnt[1], (unsigned long long)trips);
+          }
+        }
+      }
+      __syncthreads();
+      // P: publish
+      if (tid < nwork) {
+        const CWork& w = work[tid];
+        P.frec[w.f] = face_record(w.f, w.a, w.b, w.c, w.best);
+        fvert[w.f] = w.best ? (uint16_t)(0xffffu - (uint32_t)(w.best & 0xffffu)) : kNoVertex;
+        const int ch = w.f >> 6;
+        atomicOr(&s_touch[ch >> 5], 1u << (ch & 31));
+      }
+      __syncthreads();
+      // R: rebuild the touched chunks' maxima from their records
+      if (wave == 0) {
+        int cnt = 0;
+        for (int i = 0; i < cChunkIters; ++i) {
+          const int ch = lane + i * kWave;
+          const bool t = ch < LL.nchunk && ((s_touch[ch >> 5] >> (ch & 31)) & 1u);
+          const uint64_t msk = __ballot(t);
+          if (t) s_tlist[cnt + (int)__popcll(msk & ((1ull << lane) - 1))] = ch;
+          cnt += (int)__popcll(msk);
+        }
+        if (lane == 0) s_ntouch = cnt;
+        for (int i = lane; i < (cMaxChunks + 31) / 32; i += kWave) s_touch[i] = 0;
+      }
+      if (tid == 0) {
+        s_nwork = 0;
+        s_listed = 0;
+        s_next = 0;
+      }
+      __syncthreads();
+      const int nt = s_ntouch;
+      for (int j0 = wave; j0 < nt; j0 += 4 * cWaves) {
+        uint4 r[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u * cWaves;
+          const int f = (j < nt ? s_tlist[j] : 0) * 64 + lane;
+          r[u] = P.frec[f < nf ? f : nf - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int j = j0 + u * cWaves;
+          if (j >= nt) break;
+          const int f = s_tlist[j] * 64 + lane;
+          const uint64_t k = wave_max_dpp(f < nf ? rec_key(r[u]) : 0);
+          if (lane == 0) ckey[s_tlist[j]] = k;
+        }
+      }
+      const int more = s_more;
+      __syncthreads();
+      if (!more || !have_cand) break;
+      if (pass > nf / cMaxWork + 2) {           // every pass clears up to cMaxWork faces
+        if (tid == 0) {
+          *P.status = 8;
+          s_stop = 1;
+        }
+        __syncthreads();
+        break;
+      }
+      if (tid == 0) {
+        s_more = 0;
+        s_cnt[2] += 1;
+      }
+      __syncthreads();
+    }
+    if (s_ins >= n || s_stop) break;
+
+    // ---- A: the round's prefix (wave 0)
+    if (wave == 0) {
+      if (lane == 0) s_cnt[3] += 1;
+      // the p chunks of largest maximum, in key order
+      uint64_t ck[cChunkIters];
+      uint32_t cm = 0;
+#pragma unroll
+      for (int i = 0; i < cChunkIters; ++i) {
+        const int ch = lane + i * kWave;
+        ck[i] = ch < LL.nchunk ? ckey[ch] : 0;
+        cm |= ck[i] ? (1u << i) : 0u;
+      }
+      int nsel = 0;
+      for (int s = 0; s < p; ++s) {
+        uint64_t lm = 0;
+        int li = 0;
+#pragma unroll
+        for (int i = 0; i < cChunkIters; ++i) {
+          const bool c = ((cm >> i) & 1u) && ck[i] > lm;
+          lm = c ? ck[i] : lm;
+          li = c ? i : li;
+        }
+        const uint64_t g = wave_max_dpp(lm);
+        if (g == 0) break;
+        if (lm == g) {
+          s_sel[nsel] = lane + li * kWave;
+          cm &= ~(1u << li);
+        }
+        ++nsel;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      // their records' keys (lane l holds record l of each chosen chunk)
+      uint64_t kk[kMaxPrefix];
+#pragma unroll
+      for (int j = 0; j < kMaxPrefix; ++j) {
+        const int f = (j < nsel ? s_sel[j] : 0) * 64 + lane;
+        kk[j] = (j < nsel && f < nf) ? rec_key(P.frec[f]) : 0;
+      }
+      // the p best keys, in order; a pair whose vertex an earlier kept pair has is dropped
+      uint64_t lk[kMaxPrefix];
+      int nl = 0;
+      for (int s = 0; s < p; ++s) {
+        uint64_t lm = 0;
+        int lj = 0;
+#pragma unroll
+        for (int j = 0; j < kMaxPrefix; ++j) {
+          const bool c = kk[j] > lm;
+          lm = c ? kk[j] : lm;
+          lj = c ? j : lj;
+        }
+        const uint64_t g = wave_max_dpp(lm);
+        if (g == 0) break;
+#pragma unroll
+        for (int j = 0; j < kMaxPrefix; ++j) kk[j] = (lm == g && j == lj) ? 0 : kk[j];
+        bool dup = false;
+#pragma unroll
+        for (int q = 0; q < kMaxPrefix; ++q) dup |= q < nl && (lk[q] & 0xffffu) == (g & 0xffffu);
+        if (!dup) {
+#pragma unroll
+          for (int q = 0; q < kMaxPrefix; ++q) lk[q] = q == nl ? g : lk[q];
+          ++nl;
+        }
+      }
+      uint64_t mine = 0;
+#pragma unroll
+      for (int q = 0; q < kMaxPrefix; ++q) mine = q == lane ? lk[q] : mine;
+      if (lane < nl) s_lrec[lane] = P.frec[0xffff - (int)((uint32_t)mine >> 16)];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (lane == 0) {
+        if (nl == 0) {
+          *P.status = 8;                   // no pair while vertices are left: cannot happen
+          s_stop = 1;
+        }
+        // apply the kept pairs in order
+        int ins = s_ins, F = s_F, nwk = 0;
+        for (int q = 0; q < nl; ++q) {
+          const uint4 r = s_lrec[q];
+          const int f = 0xffff - (int)(r.y >> 16), u = (int)(r.y & 0xffffu);
+          const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
+          if (ins >= n || is_ins(bits, u)) {   // a pair naming an inserted vertex: cannot happen
+            *P.status = 8;
+            s_stop = 1;
+            break;
+          }
+          bits[u >> 5] |= 1u << (u & 31);
+          const int st = ins - 4;
+          P.order[ins] = u;
+          int32_t* e = P.edges + 2 * (6 + 3 * st);
+          e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
+          int32_t* sp = P.steps + 4 * st;
+          sp[0] = f; sp[1] = x; sp[2] = y; sp[3] = z;
+          P.step_gain[st] = unord_f32(r.x);
+          fvert[f] = kNoVertex;
+          int t0 = u, t1 = x, t2 = y;
+          sort3(t0, t1, t2);
+          work[nwk++] = CWork{f, t0, t1, t2, 0};
+          t0 = u; t1 = y; t2 = z;
+          sort3(t0, t1, t2);
+          work[nwk++] = CWork{F, t0, t1, t2, 0};
+          t0 = u; t1 = x; t2 = z;
+          sort3(t0, t1, t2);
+          work[nwk++] = CWork{F + 1, t0, t1, t2, 0};
+          ++ins;
+          F += 2;
+        }
+        s_ins = ins;
+        s_F = F;
+        s_nwork = nwk;
+        s_listed = nwk;
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+  }
+
+  __syncthreads();
+  for (int f = tid; f < nf; f += cBlock) {
+    const uint4 r = P.frec[f];
+    P.faces[3 * f] = (int)(r.z & 0xffffu);
+    P.faces[3 * f + 1] = (int)(r.z >> 16);
+    P.faces[3 * f + 2] = (int)r.w;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (!s_stop) *P.status = 0;
+    if (P.stats) {
+      for (int i = 0; i < 32; ++i) P.stats[i] = 0;
+      P.stats[0] = (int32_t)(s_cnt[0] > 0x7fffffffull ? 0x7fffffffull : s_cnt[0]);
+      P.stats[1] = (int32_t)(s_cnt[1] > 0x7fffffffull ? 0x7fffffffull : s_cnt[1]);
+      P.stats[2] = (int32_t)s_cnt[2];
+      P.stats[3] = (int32_t)s_cnt[3];
+      const unsigned long long t = wall_clock64() - t_start;
+      P.stats[10] = (int32_t)(t > 0x7fffffffull ? 0x7fffffffull : t);
+    }
+  }
+}
+
+__global__ __launch_bounds__(cBlock) void tmfg_corr_kernel(LoopParams P) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  run_corr(P, smem);
+}
+
+// Batched form: as the lazy loop's, persistent workgroups take instances largest first.
+__global__ __launch_bounds__(cBlock) void batch_corr_kernel(const BatchJob* __restrict__ jobs,
+                                                            const int* __restrict__ order, int count,
+                                                            int* __restrict__ queue_head, int prefix) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  __shared__ int s_job;
+  for (;;) {
+    if (threadIdx.x == 0) s_job = atomicAdd(queue_head, 1);
+    __syncthreads();
+    const int q = s_job;
+    __syncthreads();
+    if (q >= count) break;
+    const BatchJob& J = jobs[order[q]];
+    LoopParams P;
+    P.W = J.W;
+    P.n = J.n;
+    P.idx = J.idx;
+    P.vals = J.vals;
+    P.ldi = J.ldi;
+    P.scores = J.scores;
+    P.frec = J.frec;
+    P.flags = J.flags;
+    P.order = J.order;
+    P.edges = J.edges;
+    P.steps = J.steps;
+    P.step_gain = J.step_gain;
+    P.faces = J.faces;
+    P.status = J.status;
+    P.stats = nullptr;
+    P.paper = false;
+    P.prefix = prefix;
+    run_corr(P, smem);
+    __syncthreads();
+  }
+}
+
+size_t corr_lds_bytes(int n) { return corr_layout(n).total; }
+
+hipError_t corr_init_attributes() {
+  const void* ks[2] = {(const void*)tmfg_corr_kernel, (const void*)batch_corr_kernel};
+  for (const void* k : ks) {
+    hipFuncAttributes a;
+    hipError_t e = hipFuncGetAttributes(&a, k);
+    if (e != hipSuccess) return e;
+    if (a.sharedSizeBytes + corr_lds_bytes(kMaxN) > (size_t)kLdsBytes) return hipErrorInvalidConfiguration;
+    e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t batch_corr_occupancy(int* per_cu, int n_max) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, batch_corr_kernel, cBlock, corr_lds_bytes(n_max));
+}
+
+hipError_t launch_corr(const LoopParams& p, hipStream_t s) {
+  hipLaunchKernelGGL(tmfg_corr_kernel, dim3(1), dim3(cBlock), corr_lds_bytes(p.n), s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_corr(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
+                             int n_max, int prefix, hipStream_t s) {
+  hipLaunchKernelGGL(batch_corr_kernel, dim3(grid), dim3(cBlock), corr_lds_bytes(n_max), s, jobs, order, count,
+                     queue_head, prefix);
+  return hipGetLastError();
+}
+
+}  // namespace tmfg

@@ -1,0 +1,203 @@
+// Device helpers shared by the insertion loops (internal to libtmfg): the inserted-vertex
+// bitmap, candidate keys, row and wave reductions, the seed choice, the paper's face pair,
+// and the 16-byte face record.
+#pragma once
+#include "common.h"
+
+namespace tmfg {
+namespace {
+
+constexpr int kGroup = 16;                       // lanes per face walk
+
+__device__ __forceinline__ bool is_ins(const uint32_t* bits, int u) { return (bits[u >> 5] >> (u & 31)) & 1u; }
+
+__device__ __forceinline__ uint64_t cand_key(float g, int u) {
+  return ((uint64_t)ord_f32(g) << 32) | (uint32_t)(0xffff - u);
+}
+
+__device__ __forceinline__ void sort3(int& x, int& y, int& z) {
+  int t;
+  if (x > y) { t = x; x = y; y = t; }
+  if (y > z) { t = y; y = z; z = t; }
+  if (x > y) { t = x; x = y; y = t; }
+}
+
+// Reductions inside a 16-lane row (one walk group) with DPP lane permutations, which run at
+// ALU latency instead of a trip through the LDS crossbar: pairs (quad_perm 1,0,3,2), quads
+// (quad_perm 2,3,0,1), half rows (row_half_mirror) and the whole row (row_mirror); every
+// lane of the row ends with the result. All lanes of the row must be active.
+constexpr int kDppXor1 = 0xB1;
+constexpr int kDppXor2 = 0x4E;
+constexpr int kDppHalfMirror = 0x141;
+constexpr int kDppMirror = 0x140;
+static_assert(kGroup == 16, "a walk group is one DPP row");
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+  return ((uint64_t)dpp32<CTRL>((uint32_t)(v >> 32)) << 32) | dpp32<CTRL>((uint32_t)v);
+}
+__device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
+
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+  v = max64(v, dpp64<kDppXor1>(v));
+  v = max64(v, dpp64<kDppXor2>(v));
+  v = max64(v, dpp64<kDppHalfMirror>(v));
+  return max64(v, dpp64<kDppMirror>(v));
+}
+__device__ __forceinline__ int group_min_i32(int x) {
+  x = min(x, (int)dpp32<kDppXor1>((uint32_t)x));
+  x = min(x, (int)dpp32<kDppXor2>((uint32_t)x));
+  x = min(x, (int)dpp32<kDppHalfMirror>((uint32_t)x));
+  return min(x, (int)dpp32<kDppMirror>((uint32_t)x));
+}
+// Wave-wide maximum: row maxima by DPP, then the four rows read out lane by lane.
+__device__ __forceinline__ uint64_t wave_max_dpp(uint64_t v) {
+  v = group_max_u64(v);
+  uint64_t m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 16 * r);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 16 * r);
+    m = max64(m, ((uint64_t)hi << 32) | lo);
+  }
+  return m;
+}
+
+// Seed (Algorithm 1 and Algorithm 2, first comment): the four vertices of largest score,
+// ties to the lower id, in rank order, into s_seed[0..3]. The whole workgroup of BLOCK
+// threads takes part; s_part and s_vpart hold one entry per wave.
+template <int BLOCK>
+__device__ __forceinline__ void seed_top4(const double* scores, int n, int* s_seed, uint64_t* s_part, int* s_vpart) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int r = 0; r < 4; ++r) {
+    uint64_t bk = 0;
+    int bv = 0x7fffffff;
+    for (int v = tid; v < n; v += BLOCK) {
+      bool taken = false;
+      for (int q = 0; q < r; ++q) taken |= (s_seed[q] == v);
+      if (taken) continue;
+      const uint64_t k = ord_f64(scores[v]);
+      if (k > bk || (k == bk && v < bv)) {
+        bk = k;
+        bv = v;
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t ok = ((uint64_t)__shfl_xor((uint32_t)(bk >> 32), off, kWave) << 32) |
+                          __shfl_xor((uint32_t)bk, off, kWave);
+      const int ov = __shfl_xor(bv, off, kWave);
+      if (ok > bk || (ok == bk && ov < bv)) {
+        bk = ok;
+        bv = ov;
+      }
+    }
+    if (lane == 0) {
+      s_part[wave] = bk;
+      s_vpart[wave] = bv;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint64_t k = s_part[0];
+      int v = s_vpart[0];
+      for (int w = 1; w < BLOCK / kWave; ++w)
+        if (s_part[w] > k || (s_part[w] == k && s_vpart[w] < v)) {
+          k = s_part[w];
+          v = s_vpart[w];
+        }
+      s_seed[r] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// The paper's pair of one face (Section 4.1, Algorithm 2), by a group of kGroup lanes: the
+// candidates are the MaxCorrs of the three corners, each the first uninserted entry of the
+// corner's sorted row, found from the corner's cached position kGroup * 8 entries at a time
+// (8 ids per lane, bitmap only); the pair is the candidate of largest gain, ties to the
+// lowest id (a vertex that is MaxCorrs of two corners is evaluated twice, to the same key).
+// Moves the corners' cached positions forward. 0 when no vertex is left.
+__device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* idx, int n, int ldi,
+                                               const uint32_t* bits, uint16_t* ptr, int a, int b, int c, int gl,
+                                               int* scans) {
+  const int m = n - 1;
+  const int x3[3] = {a, b, c};
+  int pos[3], cand[3];
+  bool open[3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    // every entry before it is inserted; the group agrees on one value even if another
+    // group moves the position meanwhile
+    pos[t] = group_min_i32((int)ptr[x3[t]]);
+    cand[t] = -1;
+    open[t] = pos[t] < m;
+  }
+  int trips = 0;
+  while (open[0] || open[1] || open[2]) {
+    uint4 sv[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      const int qs = (pos[t] & ~7) + gl * 8;
+      sv[t] = *(const uint4*)(idx + (size_t)x3[t] * ldi + min(qs, ldi - 8));
+    }
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (!open[t]) continue;
+      const int qs = (pos[t] & ~7) + gl * 8;
+      const uint32_t wd[4] = {sv[t].x, sv[t].y, sv[t].z, sv[t].w};
+      int fp = 0x7fffffff;          // (position << 16) | id of the first uninserted entry
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const int p = qs + j;
+        const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
+        fp = ok ? min(fp, (p << 16) | u) : fp;
+      }
+      const int f = group_min_i32(fp);
+      if (f != 0x7fffffff) {
+        pos[t] = f >> 16;
+        cand[t] = f & 0xffff;
+        open[t] = false;
+      } else {
+        pos[t] = min((pos[t] & ~7) + kGroup * 8, m);
+        open[t] = pos[t] < m;
+      }
+    }
+    ++trips;
+  }
+  if (gl == 0) {
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (pos[t] > (int)ptr[x3[t]]) ptr[x3[t]] = (uint16_t)pos[t];
+  }
+  // lane t < 3 evaluates the candidate of corner t, all three similarities from W
+  const int t = gl < 3 ? gl : 0;
+  const int u = t == 0 ? cand[0] : t == 1 ? cand[1] : cand[2];
+  const int uc = u >= 0 ? u : 0;
+  const float wa = W[(size_t)a * n + uc], wb = W[(size_t)b * n + uc], wc = W[(size_t)c * n + uc];
+  const uint64_t k = (gl < 3 && u >= 0) ? cand_key((wa + wb) + wc, u) : 0;
+  *scans += trips;
+  return group_max_u64(k);
+}
+
+__device__ __forceinline__ uint64_t rec_key(const uint4& r) { return ((uint64_t)r.x << 32) | r.y; }
+__device__ __forceinline__ int rec_face(const uint4& r) { return 0xffff - (int)(r.y >> 16); }
+__device__ __forceinline__ int rec_vertex(const uint4& r) { return (int)(r.y & 0xffffu); }
+
+// A face record: {ord(gain), (0xffff - face) << 16 | vertex, a | b << 16, c}. Its first two
+// words, read as one 64-bit key, order records by (gain desc, face id asc); 0 means no pair.
+__device__ __forceinline__ uint4 face_record(int f, int a, int b, int c, uint64_t best) {
+  uint4 rec;
+  rec.x = (uint32_t)(best >> 32);
+  rec.y = best ? ((uint32_t)(0xffff - f) << 16) | (0xffffu - (uint32_t)(best & 0xffffu)) : 0u;
+  rec.z = (uint32_t)a | ((uint32_t)b << 16);
+  rec.w = (uint32_t)c;
+  return rec;
+}
+
+}  // namespace
+}  // namespace tmfg

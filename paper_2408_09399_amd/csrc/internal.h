@@ -46,9 +46,12 @@ struct LoopParams {
   int32_t* status;
   int32_t* stats;          // optional, 24 counters (see tmfg_plan_stats)
   bool paper;              // the paper's face rule (Algorithm 2) instead of the exact one
+  int prefix;              // > 0: corr-tmfg (Algorithm 1) with this prefix size
 };
+constexpr int kMaxPrefix = 16;   // largest corr-tmfg prefix size
 hipError_t launch_loop(const LoopParams& p, hipStream_t s);
 size_t loop_lds_bytes(int n);
+hipError_t launch_corr(const LoopParams& p, hipStream_t s);
 
 }  // namespace tmfg
 
@@ -101,11 +104,15 @@ bool sort_config_fits(int cfg, int cls);
 // of job indices, largest first) through the counter at *queue_head.
 hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
                              int n_max, bool paper, hipStream_t s);
+hipError_t launch_batch_corr(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
+                             int n_max, int prefix, hipStream_t s);
 int corr_tiles(int n);                        // upper-triangular correlation tiles of n rows
 hipError_t sort_init_attributes();            // LDS limits of the kernels (set once)
 hipError_t loop_init_attributes();
+hipError_t corr_init_attributes();
 hipError_t init_attributes_once();            // both of the above, once per process
 hipError_t batch_loop_occupancy(int* per_cu, int n_max, bool paper);   // loop workgroups per CU
+hipError_t batch_corr_occupancy(int* per_cu, int n_max);
 void record_hip_error(int e);                 // for tmfg_last_hip_error()
 int validate_tiles(int n);                    // 32x32 validation tiles of an n x n matrix
 

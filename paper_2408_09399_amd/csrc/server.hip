@@ -161,7 +161,7 @@ hipError_t dispatch(tmfg_server s, Slot& slot) {
   L.d_ints = (const int*)(slot.d_desc + s->jobs_bytes);
   L.d_queue = (int*)(slot.d_desc + s->jobs_bytes + tmfg::align256(s->ints_cap * 4));
   hipError_t e;
-  if ((e = tmfg::batch_grid(s->device, count, spec.n_max, spec.paper, &L.grid)) != hipSuccess) return e;
+  if ((e = tmfg::batch_grid(s->device, count, spec.n_max, spec.paper, spec.prefix, &L.grid)) != hipSuccess) return e;
   const hipStream_t st = slot.stream;
   if ((e = hipMemcpyAsync(L.d_jobs, hj, sizeof(tmfg::BatchJob) * count, hipMemcpyHostToDevice, st)) != hipSuccess)
     return e;

@@ -43,7 +43,23 @@ def test_host_side_argument_errors():
     assert lib.tmfg_plan_create(ctypes.byref(h), 3, 10, 0) == 2
     assert lib.tmfg_plan_create(ctypes.byref(h), 20481, 10, 0) == 2
     assert lib.tmfg_plan_create(ctypes.byref(h), 100, 1, 0) == 2
-    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1 << 9) == 1
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1 << 10) == 1
+    # face-rule flags: corr-tmfg needs a prefix in [1, 16], and excludes the paper's heap rule
+    # (a well-formed job with placeholder pointers: a bad rule is rejected before any HIP call,
+    # a good one gets as far as the HIP runtime, which has no device here)
+    jobs = (binding.Job * 1)()
+    j = jobs[0]
+    j.n, j.L = 10, 8
+    j.X = j.order = j.edges = j.steps = j.step_gain = j.faces = j.status = 256
+    pj = ctypes.cast(jobs, ctypes.c_void_p)
+    for bad in (binding.RULE_CORR, binding.rule_corr_prefix(17), binding.rule_corr_prefix(255),
+                binding.rule_corr_prefix(2) | binding.RULE_PAPER, 3 << binding.PREFIX_SHIFT):
+        assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, bad) == 1, hex(bad)
+        assert lib.tmfg_batch_create(ctypes.byref(h), pj, 1, bad) == 1, hex(bad)
+    import torch
+    if torch.cuda.device_count() == 0:       # with a device this would build a real batch
+        for good in (binding.rule_corr_prefix(1), binding.rule_corr_prefix(16), binding.RULE_PAPER):
+            assert lib.tmfg_batch_create(ctypes.byref(h), pj, 1, good) != 1, hex(good)
     assert lib.tmfg_build(None, None, None) == 1
     assert lib.tmfg_correlation(None, None, 10, 10, None, None, None) == 1
     assert lib.tmfg_sort_rows(None, None, 10, None, None, 16, None) == 1
