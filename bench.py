@@ -41,8 +41,10 @@ def parse():
     ap.add_argument("--fifo", action="store_true", help="c5: dispatch strictly in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=1500)
-    ap.add_argument("--rule", default="exact", choices=["exact", "paper"],
-                    help="face rule: exact greedy, or the paper's candidate rule (Algorithm 2)")
+    ap.add_argument("--rule", default="exact", choices=["exact", "paper", "corr"],
+                    help="face rule: exact greedy, the paper's heap rule (Algorithm 2), or corr-tmfg "
+                         "with a prefix size (Algorithm 1)")
+    ap.add_argument("--prefix", type=int, default=1, help="corr-tmfg prefix size (1..16)")
     ap.add_argument("--edge-sums", action="store_true",
                     help="edge-sum study: exact vs paper face rule on the single-build workloads")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -223,7 +225,7 @@ def bench_batch(args):
             sys.exit(1)
         return wall
 
-    rule = tm.RULE_PAPER if args.rule == "paper" else 0
+    rule = rule_flags(tm, args.rule, args.prefix)
     default = tm.Batch([("X", x) for x in Xs], flags=rule)
     wall_default = timed(default)
     default.close()
@@ -252,7 +254,7 @@ def bench_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(inst)} planted-cluster instances, n log-uniform in [64, 4096], "
                                f"L uniform in [64, 512]", "instances": len(inst),
-                   "sum_n": int(sum(s.X.shape[0] for s in inst)), "rule": args.rule},
+                   "sum_n": int(sum(s.X.shape[0] for s in inst)), "rule": rule_name(args)},
         "insertions_per_s": round(insertions / per, 1),
         "autotuned": tuned_cfg,
         "default_launch": {"ms_per_step": round(wall_default / args.steps * 1e3, 3),
@@ -325,7 +327,7 @@ def bench_serve(args):
     n_max = max(X.shape[0] for X in Xs)
     srv = tm.Server(hbm_budget=96 << 30, host_budget=4 << 30, max_batch=args.max_batch, n_streams=args.streams,
                     n_max=n_max, L_max=256, flags=(tm.SERVER_FIFO if args.fifo else 0) |
-                    (tm.SERVER_RULE_PAPER if args.rule == "paper" else 0))
+                    rule_flags(tm, args.rule, args.prefix))
     _replay(srv, Xs[: warm], t_unit, None, 0)                # first use: code paths, caches
     sat = _replay(srv, Xs, t_unit, None, 0)                  # everything at once
     rates = {}
@@ -341,11 +343,11 @@ def bench_serve(args):
     if args.no_serial:
         print(json.dumps({"metric": "p50/p99 latency at fixed QPS (request server, continuous batching)",
                           "server": {"max_batch": args.max_batch, "n_streams": args.streams,
-                                     "policy": "fifo" if args.fifo else "size classes"}, "rule": args.rule,
+                                     "policy": "fifo" if args.fifo else "size classes"}, "rule": rule_name(args),
                           "saturated": sat, "at_rate": rates}))
         return
     dev = torch.device("cuda:0")
-    plan = tm.Plan(n_max, 256, tm.RULE_PAPER if args.rule == "paper" else 0)
+    plan = tm.Plan(n_max, 256, rule_flags(tm, args.rule, args.prefix))
     service = np.empty(len(Xs))
     for i, X in enumerate(Xs):
         t0 = time.perf_counter()
@@ -371,11 +373,15 @@ def bench_serve(args):
         "config": {"workload": f"Poisson arrivals of {len(Xs)} rolling-window requests, n log-uniform in "
                                f"[100, 8000], L=256, from host memory", "requests": len(Xs),
                    "server": {"max_batch": args.max_batch, "n_streams": args.streams,
-                              "policy": "fifo" if args.fifo else "size classes"}, "rule": args.rule},
+                              "policy": "fifo" if args.fifo else "size classes"}, "rule": rule_name(args)},
         "saturated": sat, "at_rate": rates,
         "serial_plain": {"builds_per_s": round(len(Xs) / float(service.sum()), 1), "at_rate": serial},
     }
     print(json.dumps(out))
+
+
+def rule_name(args) -> str:
+    return f"corr p={args.prefix}" if args.rule == "corr" else args.rule
 
 
 def edge_sum(W, edges) -> float:
@@ -405,27 +411,40 @@ def rule_run(tm, X, steps, flags):
     return res, float(np.median(loops)), stats
 
 
-def paper_rule_summary(tm, X, res_exact, loop_ms_exact, steps) -> dict:
-    """The paper's face rule (Algorithm 2) on the same input: loop rate, counters, and its
-    edge sum against the exact rule's."""
+def rule_flags(tm, rule: str, prefix: int) -> int:
+    return {"exact": 0, "paper": tm.RULE_PAPER, "corr": tm.rule_corr_prefix(prefix)}[rule]
+
+
+def rule_summary(tm, X, res_exact, loop_ms_exact, steps, rule: str, prefix: int = 1) -> dict:
+    """Another face rule on the same input (the paper's heap rule, Algorithm 2, or corr-tmfg
+    with a prefix size, Algorithm 1): loop rate, counters, and its edge sum against the exact
+    rule's."""
     n = X.shape[0]
-    res, loop_ms, st = rule_run(tm, X, steps, tm.RULE_PAPER)
+    res, loop_ms, st = rule_run(tm, X, steps, rule_flags(tm, rule, prefix))
     es_p, es_e = edge_sum(res.W, res.edges), edge_sum(res_exact.W, res_exact.edges)
     oe = res_exact.order.cpu().numpy()
     op = res.order.cpu().numpy()
     diff = np.flatnonzero(oe != op)
-    return {"loop_ms": round(loop_ms, 3), "loop_insertions_per_s": round((n - 4) / (loop_ms * 1e-3), 1),
-            "exact_loop_ms": round(loop_ms_exact, 3),
-            "edge_sum": round(es_p, 6), "exact_edge_sum": round(es_e, 6),
-            "edge_sum_rel_diff": float(f"{(es_p - es_e) / abs(es_e):.4e}"),
-            "first_order_difference": int(diff[0]) if diff.size else None,
-            "stats": {"stale_recomputes": st[0], "row_scans": st[1], "phases": st[3],
-                      "stale_top_phases": st[20], "work_overflow_phases": st[21],
-                      "chunk_overflow_phases": st[22], "not_committed": st[23]}}
+    out = {"rule": rule if rule != "corr" else f"corr p={prefix}",
+           "loop_ms": round(loop_ms, 3), "loop_insertions_per_s": round((n - 4) / (loop_ms * 1e-3), 1),
+           "exact_loop_ms": round(loop_ms_exact, 3),
+           "edge_sum": round(es_p, 6), "exact_edge_sum": round(es_e, 6),
+           "edge_sum_rel_diff": float(f"{(es_p - es_e) / abs(es_e):.4e}"),
+           "first_order_difference": int(diff[0]) if diff.size else None}
+    if rule == "paper":
+        out["stats"] = {"stale_recomputes": st[0], "row_scans": st[1], "phases": st[3],
+                        "stale_top_phases": st[20], "work_overflow_phases": st[21],
+                        "chunk_overflow_phases": st[22], "not_committed": st[23]}
+    else:
+        out["stats"] = {"recomputes": st[0], "row_scans": st[1], "extra_passes": st[2], "rounds": st[3],
+                        "us": {"scan": st[5], "pairs": st[6], "publish": st[7], "rebuild": st[8],
+                               "select": st[9]}}
+    return out
 
 
 def bench_edge_sums(args):
-    """Edge-sum study (Section 5.2, Figure 7 analogue): exact greedy vs the paper's rule."""
+    """Edge-sum study (Section 5.2, Figure 7 analogue): exact greedy against the paper's heap
+    rule and corr-tmfg with prefix sizes 1, 4 and 16."""
     import torch
     import paper_2408_09399_amd as tm
     rows = []
@@ -433,10 +452,11 @@ def bench_edge_sums(args):
         s = workload(name)
         X = torch.from_numpy(s.X).to(torch.device("cuda:0"))
         res_e, ms_e, _ = rule_run(tm, X, args.steps, 0)
-        row = paper_rule_summary(tm, X, res_e, ms_e, args.steps)
-        row["workload"] = f"{s.name}: n={s.X.shape[0]}, L={s.X.shape[1]}"
-        rows.append(row)
-        print(json.dumps(row), flush=True)
+        for rule, prefix in [("paper", 1), ("corr", 1), ("corr", 4), ("corr", 16)]:
+            row = rule_summary(tm, X, res_e, ms_e, args.steps, rule, prefix)
+            row["workload"] = f"{s.name}: n={s.X.shape[0]}, L={s.X.shape[1]}"
+            rows.append(row)
+            print(json.dumps(row), flush=True)
         del X, res_e
         torch.cuda.empty_cache()
     print(json.dumps({"edge_sums": rows}))
@@ -462,7 +482,7 @@ def main():
     n, L = s.X.shape
     dev = torch.device("cuda:0")
     X = torch.from_numpy(s.X).to(dev)
-    plan = tm.Plan(n, L, tm.TIMING | (tm.RULE_PAPER if args.rule == "paper" else 0))
+    plan = tm.Plan(n, L, tm.TIMING | rule_flags(tm, args.rule, args.prefix))
     res = tm.alloc_result(n, dev, keep_w=True)
     stream = torch.cuda.current_stream()
 
@@ -519,7 +539,7 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"single TMFG build from planted-cluster random-walk series, "
-                               f"n={n}, L={L} ({s.name})", "n": n, "L": L, "rule": args.rule},
+                               f"n={n}, L={L} ({s.name})", "n": n, "L": L, "rule": rule_name(args)},
         "phases_ms": {"similarity": round(ph[0], 3), "seed_scores": round(ph[1], 3),
                       "row_sort": round(ph[2], 3), "insertion_loop": round(ph[3], 3),
                       "total": round(ph[4], 3)},
@@ -538,7 +558,9 @@ def main():
         "face_sweep_refresh": sweep_refresh(tm, plan, res.W, res, n, stream),
     }
     if args.rule == "exact":
-        out["paper_rule"] = paper_rule_summary(tm, X, res, float(ph[3]), min(args.steps, 3))
+        k = min(args.steps, 3)
+        out["paper_rule"] = rule_summary(tm, X, res, float(ph[3]), k, "paper")
+        out["corr_rule"] = [rule_summary(tm, X, res, float(ph[3]), k, "corr", p) for p in (1, 16)]
     if not args.no_cpu_baseline and args.rule == "exact":
         out["cpu_baseline"] = cpu_baseline(s.X, res.W.cpu().numpy(), args.cpu_sample_steps)
     plan.close()

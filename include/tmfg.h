@@ -148,7 +148,8 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    entry of the corners' sorted rows instead of walk rounds. Under TMFG_RULE_CORR only these
    are kept: [0] faces recomputed because their pair vertex was inserted, [1] row scans,
    [2] extra passes (a round with more faces to recompute than one pass takes), [3] rounds,
-   [10] microseconds of the kernel; the others read 0. */
+   [5..9] microseconds in the scan for faces to recompute, their pairs, publishing,
+   rebuilding chunk maxima and selection, [10] microseconds of the kernel; the others read 0. */
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
 
 /* ---- Batches: many independent builds in one graph replay ------------------------ */
@@ -203,7 +204,8 @@ typedef struct {
   int32_t n_streams;      /* dispatches in flight at once (1..4) */
   int32_t n_max;          /* largest n accepted (4..20480) */
   int32_t L_max;          /* largest L accepted (>= 2) */
-  uint32_t flags;         /* TMFG_SERVER_FIFO, TMFG_SERVER_RULE_PAPER, or 0 */
+  uint32_t flags;         /* TMFG_SERVER_FIFO, a face rule (TMFG_SERVER_RULE_PAPER, or the plan
+                             flags TMFG_RULE_PAPER or TMFG_RULE_CORR_PREFIX(p)), or 0 */
 } tmfg_server_config;
 
 /* Server flags. By default a dispatch takes the oldest waiting request and the waiting

@@ -20,7 +20,7 @@
 //      and applies them; the new faces become work items;
 //   S  every face whose pair vertex is inserted is found by a scan of the pair vertices and
 //      becomes a work item (at most one per thread; more wait for another pass);
-//   B  each work item's pair, one group of 16 lanes per face;
+//   B  each work item's pair, one group of cGroup lanes per face;
 //   P  records and pair vertices are published; the chunks they touch are marked;
 //   R  the maxima of the touched chunks are rebuilt from their records.
 #include "common.h"
@@ -36,6 +36,8 @@ constexpr int cMaxWork = cBlock;                 // faces recomputed per pass, o
 constexpr int cMaxChunks = (2 * kMaxN - 4 + 63) / 64;
 constexpr int cChunkIters = (cMaxChunks + kWave - 1) / kWave;
 constexpr uint16_t kNoVertex = 0xffff;
+constexpr int cGroup = 8;                        // lanes per face pair (a half row)
+constexpr int cLoads = 1;                        // 16-byte loads per lane and corner in a row scan
 static_assert(kMaxPrefix <= kWave, "the prefix fits one wave's selection");
 
 struct CorrLds {
@@ -71,11 +73,13 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   __shared__ uint64_t s_part[cWaves];
   __shared__ int s_vpart[cWaves];
   // counters: [0] stale recomputes [1] row-scan trips [2] extra passes [3] rounds
-  __shared__ unsigned long long s_cnt[4];
+  // [4..8] clock ticks in the scan, the pairs, publishing, rebuilding and selection
+  __shared__ unsigned long long s_cnt[9];
+  __shared__ unsigned long long s_t0;
 
   const int n = P.n, p = P.prefix;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int gl = lane & (kGroup - 1);
+  const int gl = lane & (cGroup - 1);
   const CorrLds LL = corr_layout(n);
   uint64_t* ckey = (uint64_t*)(smem + LL.off_ckey);
   uint32_t* bits = (uint32_t*)(smem + LL.off_bits);
@@ -99,7 +103,14 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   for (int i = tid; i < n; i += cBlock) ptr[i] = 0;
   for (int i = tid; i < (int)((LL.total - LL.off_fvert) / 2); i += cBlock) fvert[i] = kNoVertex;
   for (int i = tid; i < (cMaxChunks + 31) / 32; i += cBlock) s_touch[i] = 0;
-  if (tid < 4) s_cnt[tid] = 0;
+  if (tid < 9) s_cnt[tid] = 0;
+  if (tid == 0) s_t0 = wall_clock64();
+#define CORR_LAP(slot)                    \
+  if (tid == 0) {                         \
+    const uint64_t t1_ = wall_clock64();  \
+    s_cnt[slot] += t1_ - s_t0;            \
+    s_t0 = t1_;                           \
+  }
 
   seed_top4<cBlock>(P.scores, n, s_seed, s_part, s_vpart);
   if (tid == 0) {
@@ -152,20 +163,21 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
         }
         __syncthreads();
         if (tid == 0) s_cnt[0] += (unsigned long long)((s_nwork < cMaxWork ? s_nwork : cMaxWork) - s_listed);
+        CORR_LAP(4);
       }
       const int nwork = s_nwork < cMaxWork ? s_nwork : cMaxWork;
       // B: the pair of every listed face
       for (;;) {
         int base = 0;
-        if (lane == 0) base = atomicAdd(&s_next, kWave / kGroup);
+        if (lane == 0) base = atomicAdd(&s_next, kWave / cGroup);
         base = __builtin_amdgcn_readfirstlane(base);
         if (base >= nwork) break;
-        const int item = base + (lane / kGroup);
+        const int item = base + (lane / cGroup);
         if (item < nwork) {
           CWork& w = work[item];
           int trips = 0;
           const uint64_t best =
-              have_cand ? paper_face(P.W, P.idx, n, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
+              have_cand ? paper_face<cGroup, cLoads>(P.W, P.idx, n, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
           if (gl == 0) {
             w.best = best;
             atomicAdd(&s_cnt[1], (unsigned long long)trips);
@@ -173,6 +185,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
         }
       }
       __syncthreads();
+      CORR_LAP(5);
       // P: publish
       if (tid < nwork) {
         const CWork& w = work[tid];
@@ -182,6 +195,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
         atomicOr(&s_touch[ch >> 5], 1u << (ch & 31));
       }
       __syncthreads();
+      CORR_LAP(6);
       // R: rebuild the touched chunks' maxima from their records
       if (wave == 0) {
         int cnt = 0;
@@ -221,6 +235,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       }
       const int more = s_more;
       __syncthreads();
+      CORR_LAP(7);
       if (!more || !have_cand) break;
       if (pass > nf / cMaxWork + 2) {           // every pass clears up to cMaxWork faces
         if (tid == 0) {
@@ -352,8 +367,10 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       }
     }
     __syncthreads();
+    CORR_LAP(8);
     if (s_stop) break;
   }
+#undef CORR_LAP
 
   __syncthreads();
   for (int f = tid; f < nf; f += cBlock) {
@@ -371,6 +388,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       P.stats[1] = (int32_t)(s_cnt[1] > 0x7fffffffull ? 0x7fffffffull : s_cnt[1]);
       P.stats[2] = (int32_t)s_cnt[2];
       P.stats[3] = (int32_t)s_cnt[3];
+      for (int i = 0; i < 5; ++i) P.stats[5 + i] = (int32_t)(s_cnt[4 + i] > 0x7fffffffull ? 0x7fffffffull : s_cnt[4 + i]);
       const unsigned long long t = wall_clock64() - t_start;
       P.stats[10] = (int32_t)(t > 0x7fffffffull ? 0x7fffffffull : t);
     }

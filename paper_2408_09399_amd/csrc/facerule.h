@@ -42,18 +42,28 @@ __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
 }
 __device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
+// The same over groups of G = 4, 8 or 16 lanes (quads, half rows, rows).
+template <int G>
 __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
+  static_assert(G == 4 || G == 8 || G == 16, "a group is a quad, a half row or a row");
   v = max64(v, dpp64<kDppXor1>(v));
   v = max64(v, dpp64<kDppXor2>(v));
-  v = max64(v, dpp64<kDppHalfMirror>(v));
-  return max64(v, dpp64<kDppMirror>(v));
+  if (G >= 8) v = max64(v, dpp64<kDppHalfMirror>(v));
+  if (G >= 16) v = max64(v, dpp64<kDppMirror>(v));
+  return v;
 }
+template <int G>
 __device__ __forceinline__ int group_min_i32(int x) {
+  static_assert(G == 4 || G == 8 || G == 16, "a group is a quad, a half row or a row");
   x = min(x, (int)dpp32<kDppXor1>((uint32_t)x));
   x = min(x, (int)dpp32<kDppXor2>((uint32_t)x));
-  x = min(x, (int)dpp32<kDppHalfMirror>((uint32_t)x));
-  return min(x, (int)dpp32<kDppMirror>((uint32_t)x));
+  if (G >= 8) x = min(x, (int)dpp32<kDppHalfMirror>((uint32_t)x));
+  if (G >= 16) x = min(x, (int)dpp32<kDppMirror>((uint32_t)x));
+  return x;
 }
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v) { return group_max_u64<kGroup>(v); }
+__device__ __forceinline__ int group_min_i32(int x) { return group_min_i32<kGroup>(x); }
+
 // Wave-wide maximum: row maxima by DPP, then the four rows read out lane by lane.
 __device__ __forceinline__ uint64_t wave_max_dpp(uint64_t v) {
   v = group_max_u64(v);
@@ -115,12 +125,14 @@ __device__ __forceinline__ void seed_top4(const double* scores, int n, int* s_se
   }
 }
 
-// The paper's pair of one face (Section 4.1, Algorithm 2), by a group of kGroup lanes: the
-// candidates are the MaxCorrs of the three corners, each the first uninserted entry of the
-// corner's sorted row, found from the corner's cached position kGroup * 8 entries at a time
-// (8 ids per lane, bitmap only); the pair is the candidate of largest gain, ties to the
-// lowest id (a vertex that is MaxCorrs of two corners is evaluated twice, to the same key).
-// Moves the corners' cached positions forward. 0 when no vertex is left.
+// The paper's pair of one face (Section 4.1, Algorithm 2), by a group of G lanes (gl = lane
+// within the group): the candidates are the MaxCorrs of the three corners, each the first
+// uninserted entry of the corner's sorted row, found from the corner's cached position
+// G * 8 * L entries at a time (L 16-byte loads of 8 ids per lane and corner, bitmap only);
+// the pair is the candidate of largest gain, ties to the lowest id (a vertex that is MaxCorrs
+// of two corners is evaluated twice, to the same key). Moves the corners' cached positions
+// forward. 0 when no vertex is left.
+template <int G = kGroup, int L = 1>
 __device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* idx, int n, int ldi,
                                                const uint32_t* bits, uint16_t* ptr, int a, int b, int c, int gl,
                                                int* scans) {
@@ -132,38 +144,43 @@ __device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* i
   for (int t = 0; t < 3; ++t) {
     // every entry before it is inserted; the group agrees on one value even if another
     // group moves the position meanwhile
-    pos[t] = group_min_i32((int)ptr[x3[t]]);
+    pos[t] = group_min_i32<G>((int)ptr[x3[t]]);
     cand[t] = -1;
     open[t] = pos[t] < m;
   }
   int trips = 0;
   while (open[0] || open[1] || open[2]) {
-    uint4 sv[3];
+    uint4 sv[3][L];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      const int qs = (pos[t] & ~7) + gl * 8;
-      sv[t] = *(const uint4*)(idx + (size_t)x3[t] * ldi + min(qs, ldi - 8));
+      const int qs = (pos[t] & ~7) + gl * 8 * L;
+#pragma unroll
+      for (int l = 0; l < L; ++l)
+        sv[t][l] = *(const uint4*)(idx + (size_t)x3[t] * ldi + min(qs + 8 * l, ldi - 8));
     }
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       if (!open[t]) continue;
-      const int qs = (pos[t] & ~7) + gl * 8;
-      const uint32_t wd[4] = {sv[t].x, sv[t].y, sv[t].z, sv[t].w};
+      const int qs = (pos[t] & ~7) + gl * 8 * L;
       int fp = 0x7fffffff;          // (position << 16) | id of the first uninserted entry
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-        const int p = qs + j;
-        const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
-        fp = ok ? min(fp, (p << 16) | u) : fp;
+      for (int l = 0; l < L; ++l) {
+        const uint32_t wd[4] = {sv[t][l].x, sv[t][l].y, sv[t][l].z, sv[t][l].w};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+          const int p = qs + 8 * l + j;
+          const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
+          fp = ok ? min(fp, (p << 16) | u) : fp;
+        }
       }
-      const int f = group_min_i32(fp);
+      const int f = group_min_i32<G>(fp);
       if (f != 0x7fffffff) {
         pos[t] = f >> 16;
         cand[t] = f & 0xffff;
         open[t] = false;
       } else {
-        pos[t] = min((pos[t] & ~7) + kGroup * 8, m);
+        pos[t] = min((pos[t] & ~7) + G * 8 * L, m);
         open[t] = pos[t] < m;
       }
     }
@@ -181,7 +198,7 @@ __device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* i
   const float wa = W[(size_t)a * n + uc], wb = W[(size_t)b * n + uc], wc = W[(size_t)c * n + uc];
   const uint64_t k = (gl < 3 && u >= 0) ? cand_key((wa + wb) + wc, u) : 0;
   *scans += trips;
-  return group_max_u64(k);
+  return group_max_u64<G>(k);
 }
 
 __device__ __forceinline__ uint64_t rec_key(const uint4& r) { return ((uint64_t)r.x << 32) | r.y; }

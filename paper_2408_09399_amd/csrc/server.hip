@@ -32,6 +32,12 @@
 #include <unordered_map>
 #include <vector>
 
+// The face-rule flags of a batch, from server flags: TMFG_SERVER_RULE_PAPER or the plan flags
+// TMFG_RULE_PAPER / TMFG_RULE_CORR_PREFIX(p), which the server also takes.
+static uint32_t server_rule_flags(uint32_t flags) {
+  return ((flags & TMFG_SERVER_RULE_PAPER) ? (uint32_t)TMFG_RULE_PAPER : 0u) | (flags & tmfg::kRuleFlags);
+}
+
 namespace {
 
 constexpr int kMaxSlots = 4;
@@ -147,7 +153,8 @@ hipError_t dispatch(tmfg_server s, Slot& slot) {
     j.status = (int32_t*)(res + rl.status);
   }
   tmfg::BatchSpec spec;
-  if (tmfg::batch_describe(jobs.data(), count, (s->cfg.flags & TMFG_SERVER_RULE_PAPER) ? TMFG_RULE_PAPER : 0u, spec) != TMFG_OK || spec.ints.size() > s->ints_cap)
+  if (tmfg::batch_describe(jobs.data(), count, server_rule_flags(s->cfg.flags), spec) != TMFG_OK ||
+      spec.ints.size() > s->ints_cap)
     return hipErrorInvalidValue;
   tmfg::BatchJob* hj = (tmfg::BatchJob*)slot.h_desc;
   int* hi = (int*)(slot.h_desc + s->jobs_bytes);
@@ -302,8 +309,12 @@ int64_t tmfg_server_now_ns(void) { return clock_ns(); }
 tmfg_status tmfg_server_create(tmfg_server* out, const tmfg_server_config* cfg) {
   if (!out) return TMFG_E_INVALID;
   *out = nullptr;
+  bool paper = false;
+  int prefix = 0;
   if (!cfg || cfg->hbm_budget == 0 || cfg->host_budget == 0 || cfg->max_batch < 1 || cfg->max_batch > kMaxBatch ||
-      cfg->n_streams < 1 || cfg->n_streams > kMaxSlots || (cfg->flags & ~(uint32_t)(TMFG_SERVER_FIFO | TMFG_SERVER_RULE_PAPER)))
+      cfg->n_streams < 1 || cfg->n_streams > kMaxSlots ||
+      (cfg->flags & ~(uint32_t)(TMFG_SERVER_FIFO | TMFG_SERVER_RULE_PAPER | tmfg::kRuleFlags)) ||
+      !tmfg::rule_from_flags(server_rule_flags(cfg->flags), &paper, &prefix))
     return TMFG_E_INVALID;
   if (cfg->n_max < tmfg::kMinN || cfg->n_max > tmfg::kMaxN || cfg->L_max < 2) return TMFG_E_SIZE;
   hipError_t e = tmfg::init_attributes_once();

@@ -1,7 +1,7 @@
 """corr-tmfg with a prefix size (Algorithm 1, TMFG_RULE_CORR_PREFIX(p)) on the GPU, bit-exact
 against the oracle fed the same W bytes: the hand-derived cases, random and tie-heavy
 matrices for several prefix sizes, the series path at the 200- and 5000-vertex workloads,
-and batched builds."""
+and batched and served builds."""
 import json
 import os
 
@@ -96,3 +96,24 @@ def test_batch_equals_solo_and_oracle():
             if rep == 0 and got["order"].shape[0] <= 400:
                 same_tmfg(got, oracle.tmfg_corr_lazyrows(got["W"], 3))
     b.close()
+
+
+def test_server_corr_rule():
+    rng = np.random.default_rng(6)
+    reqs = []
+    for i in range(12):
+        n = int(round(np.exp(rng.uniform(np.log(7), np.log(1200)))))
+        L = int(rng.integers(2, 260))
+        sizes = synth.dirichlet_sizes(rng, n, int(rng.integers(1, min(n, 8) + 1)))
+        reqs.append(synth.planted_clusters(n, L, sizes, (0.3, 1.0), seed=6000 + i).X)
+    flags = tm.rule_corr_prefix(2)
+    srv = tm.Server(hbm_budget=1 << 30, host_budget=128 << 20, max_batch=6, n_streams=2, n_max=2048, L_max=512,
+                    flags=flags)
+    tickets = [srv.submit(X) for X in reqs]
+    got = [srv.poll(t, wait_ms=-1) for t in tickets]
+    srv.close()
+    for X, g in zip(reqs, got):
+        assert g["status"] == 0
+        solo = tm.build(X=to_dev(X), keep_w=True, flags=flags)
+        torch.cuda.synchronize()
+        same_tmfg(g, solo.to_numpy())
