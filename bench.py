@@ -45,6 +45,9 @@ def parse():
                     help="face rule: exact greedy, the paper's heap rule (Algorithm 2), or corr-tmfg "
                          "with a prefix size (Algorithm 1)")
     ap.add_argument("--prefix", type=int, default=1, help="corr-tmfg prefix size (1..16)")
+    ap.add_argument("--dbht", action="store_true",
+                    help="DBHT clustering on the host of the GPU-built TMFG (shortest paths, bubble "
+                         "tree, complete linkage) and its ARI")
     ap.add_argument("--edge-sums", action="store_true",
                     help="edge-sum study: exact vs paper face rule on the single-build workloads")
     ap.add_argument("--calibration-copy", action="store_true",
@@ -462,6 +465,45 @@ def bench_edge_sums(args):
     print(json.dumps({"edge_sums": rows}))
 
 
+def bench_dbht(args):
+    """DBHT (Section 2; ARI of Section 5) of the TMFG the GPU builds for the workload: the host
+    library's time and ARI against the planted labels, and the oracle's time for the same."""
+    import torch
+    import paper_2408_09399_amd as tm
+    from sklearn.metrics import adjusted_rand_score
+    s = workload(args.config)
+    n, L = s.X.shape
+    X = torch.from_numpy(s.X).to(torch.device("cuda:0"))
+    plan = tm.Plan(n, L, rule_flags(tm, args.rule, args.prefix))
+    res = tm.alloc_result(n, X.device, keep_w=True)
+    tm.build(X=X, plan=plan, out=res)
+    torch.cuda.synchronize()
+    got = res.to_numpy()
+    plan.close()
+    k = len(set(s.labels.tolist()))
+    threads = min(os.cpu_count() or 1, 16)
+    times = []
+    for _ in range(max(args.steps, 1)):
+        t0 = time.perf_counter()
+        lib = tm.dbht(got["W"], got["order"], got["edges"], got["steps"], k, n_threads=threads)
+        times.append(time.perf_counter() - t0)
+    t_lib = float(np.median(times))
+    out = {"metric": "DBHT clustering of the TMFG on the host (seconds per build)", "value": round(t_lib, 3),
+           "unit": "s", "higher_is_better": False, "steps": len(times), "threads": threads,
+           "config": {"workload": f"{s.name}: n={n}, L={L}, {k} ground-truth classes", "rule": rule_name(args)},
+           "ari": round(float(adjusted_rand_score(s.labels, lib["labels"])), 4),
+           "converging_bubbles": int(len(set(lib["group"].tolist())))}
+    if not args.no_cpu_baseline:
+        from oracle import dbht as dh
+        t0 = time.perf_counter()
+        ref = dh.dbht(got["W"], got, k)
+        out["cpu_baseline"] = {"value": round(time.perf_counter() - t0, 3), "unit": "s", "cores": 1,
+                               "kind": "oracle", "sample": "the whole DBHT of the same TMFG (numpy/scipy)",
+                               "same_result": bool(all(np.array_equal(np.asarray(ref[x]), np.asarray(lib[x]))
+                                                       for x in ("labels", "group", "bubble", "linkage")))}
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -475,6 +517,8 @@ def main():
         return bench_serve(args)
     if args.edge_sums:
         return bench_edge_sums(args)
+    if args.dbht:
+        return bench_dbht(args)
     import torch
     import paper_2408_09399_amd as tm
 

@@ -298,6 +298,41 @@ tmfg_status tmfg_face_sweep(tmfg_plan plan, const float* W, int32_t n, const int
                             int32_t nfaces, const uint32_t* inserted, int32_t* best_u,
                             float* best_gain, hipStream_t stream);
 
+/* ---- Clustering on the host ------------------------------------------------------ */
+
+/* DBHT clustering of a finished TMFG (Section 2, Background: the directed bubble hierarchy
+   tree; Section 5, Evaluation: the dendrogram cut into k clusters). Runs on the host; every
+   pointer is HOST memory. Inputs: W (n x n, the float32 similarity the build used, bitwise
+   symmetric) and the build's order, edges and steps, unchanged. k: clusters of the cut,
+   1 <= k <= n. n_threads: host threads for the shortest paths (<= 0: all cores, at most 64).
+   Outputs: labels[n] (clusters numbered by their smallest vertex), and optionally the
+   dendrogram linkage[(n-1) x 4] (rows: smaller cluster id, larger id, distance, size; the
+   vertices are clusters 0..n-1 and row m makes cluster n + m), group[n] (the converging
+   bubble of each vertex) and bubble[n] (its bubble); bubble 0 is the seed clique and
+   bubble s + 1 the clique of step s. Holds n x n doubles of shortest-path lengths while it
+   runs (TMFG_E_NOMEM if that fails). TMFG_E_INVALID for a record with ids out of range.
+   Readings where the paper leaves DBHT open:
+   - edge length sqrt(2 (1 - W[i][j])) (0 if W > 1), Dijkstra path sums from the source,
+     and the distance of a pair is the sum from its smaller id;
+   - bubble s + 1's parent is the bubble that made the face step s split (the seed's faces:
+     bubble 0), and that face is their separating triangle;
+   - a tree edge points to the side, child (the vertices inserted in the child's subtree) or
+     parent (the other vertices off the triangle), whose TMFG edges to the triangle have the
+     strictly larger W sum (float64, triangle vertex ascending, then neighbour ascending);
+     a tie points to the parent;
+   - converging bubbles have no outgoing edge; a vertex's group is, of the converging bubbles
+     reachable from the bubbles containing it, the one its TMFG edges weigh most (sum of W to
+     the bubble's other vertices, ascending), ties to the lowest id; its bubble is, of the
+     bubbles containing it that reach its group, the one of least summed path length to the
+     bubble's four vertices, ties to the lowest id;
+   - complete linkage (largest member-pair path length; the closest pair first, ties to the
+     lowest (smaller id, larger id)) joins each (group, bubble) cell, then the cells of each
+     group, then the groups, cells and groups in ascending bubble-id order; the cut undoes
+     the last k - 1 merges of that sequence. */
+tmfg_status tmfg_dbht(int32_t n, const float* W, const int32_t* order, const int32_t* edges,
+                      const int32_t* steps, int32_t k, int32_t n_threads, int32_t* labels,
+                      double* linkage, int32_t* group, int32_t* bubble);
+
 /* ---- Diagnostics ------------------------------------------------------------------ */
 
 const char* tmfg_status_string(tmfg_status s);

@@ -64,6 +64,7 @@ SIGNATURES = {
     "tmfg_server_stats": (_I, [_P, _P, _I]),
     "tmfg_server_destroy": (_I, [_P]),
     "tmfg_server_now_ns": (ctypes.c_int64, []),
+    "tmfg_dbht": (_I, [_I, _P, _P, _P, _P, _I, _I, _P, _P, _P, _P]),
     "tmfg_status_string": (ctypes.c_char_p, [_I]),
     "tmfg_last_hip_error": (ctypes.c_int, []),
 }
@@ -441,3 +442,27 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def dbht(W, order, edges, steps, k: int, n_threads: int = 0) -> dict:
+    """DBHT clustering of a finished TMFG on the host (tmfg_dbht). Inputs are numpy arrays
+    or tensors (copied to host memory); returns labels, linkage, group and bubble."""
+    import numpy as np
+
+    def host(a, dtype):
+        if hasattr(a, "detach"):
+            a = a.detach().cpu().numpy()
+        return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+    Wh = host(W, np.float32)
+    n = Wh.shape[0]
+    order_h, edges_h = host(order, np.int32), host(edges, np.int32).reshape(-1, 2)
+    steps_h = host(steps, np.int32).reshape(-1, 4) if n > 4 else np.zeros((0, 4), np.int32)
+    labels = np.empty(n, np.int32)
+    linkage = np.empty((max(n - 1, 0), 4), np.float64)
+    group = np.empty(n, np.int32)
+    bubble = np.empty(n, np.int32)
+    p = lambda a: a.ctypes.data if a.size else None
+    _check(_lib().tmfg_dbht(n, p(Wh), p(order_h), p(edges_h), p(steps_h), int(k), int(n_threads), p(labels),
+                            p(linkage), p(group), p(bubble)), "tmfg_dbht")
+    return {"labels": labels, "linkage": linkage, "group": group, "bubble": bubble}
