@@ -30,7 +30,7 @@
 namespace tmfg {
 
 namespace {
-constexpr int cBlock = 512;
+constexpr int cBlock = 1024;
 constexpr int cWaves = cBlock / kWave;
 constexpr int cMaxWork = cBlock;                 // faces recomputed per pass, one per thread
 constexpr int cMaxChunks = (2 * kMaxN - 4 + 63) / 64;
@@ -256,12 +256,16 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
     // ---- A: the round's prefix (wave 0)
     if (wave == 0) {
       if (lane == 0) s_cnt[3] += 1;
+      // the lane index is made opaque so that the chunk addresses are formed anew each round
+      // rather than held in registers across the whole loop
+      int sl_lane = lane;
+      asm volatile("" : "+v"(sl_lane));
       // the p chunks of largest maximum, in key order
       uint64_t ck[cChunkIters];
       uint32_t cm = 0;
 #pragma unroll
       for (int i = 0; i < cChunkIters; ++i) {
-        const int ch = lane + i * kWave;
+        const int ch = sl_lane + i * kWave;
         ck[i] = ch < LL.nchunk ? ckey[ch] : 0;
         cm |= ck[i] ? (1u << i) : 0u;
       }
@@ -278,7 +282,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
         const uint64_t g = wave_max_dpp(lm);
         if (g == 0) break;
         if (lm == g) {
-          s_sel[nsel] = lane + li * kWave;
+          s_sel[nsel] = sl_lane + li * kWave;
           cm &= ~(1u << li);
         }
         ++nsel;

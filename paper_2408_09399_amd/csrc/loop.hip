@@ -43,7 +43,7 @@
 namespace tmfg {
 
 namespace {
-constexpr int kBlock = 512;
+constexpr int kBlock = 1024;
 constexpr int kWaves = kBlock / kWave;
 constexpr int kGroups = kBlock / kGroup;         // face walks in flight
 constexpr int kScan = 4;                         // list entries per lane and round
@@ -733,9 +733,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       // floor after an insertion and the stale chunks to reload all come from these.
       uint32_t khi[kChunkIters], klo[kChunkIters];
       uint32_t insm = 0;
+      // the lane index is made opaque here so that the chunk addresses below are formed anew
+      // each phase rather than held in registers across the whole loop
+      int sl_lane = lane;
+      asm volatile("" : "+v"(sl_lane));
 #pragma unroll
       for (int i = 0; i < kChunkIters; ++i) {
-        const int ch = lane + i * kWave;
+        const int ch = sl_lane + i * kWave;
         const uint4 r = cmax[ch < LL.nchunk ? ch : 0];
         khi[i] = ch < LL.nchunk ? r.x : 0u;
         klo[i] = ch < LL.nchunk ? r.y : 0u;
@@ -805,10 +809,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           kf2 = wave_max_dpp(kf2);
           if (Paper) {
             uint64_t rest = 0;
-            ns = pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane, &rest);
+            ns = pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, sl_lane, &rest);
             if (lane == 0) s_unloaded = s_rest = rest;
           } else {
-            ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, lane);
+            ns = append_stale_chunks(khi, klo, insm, LL.nchunk, kf2, c1, c2, sel, ns, sl_lane);
           }
         }
         if (lane == 0) {
@@ -831,8 +835,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         if (lane == 0) s_cnt[16] += 1;
         if (lane == 0) sel[0] = c1;
         uint64_t rest = 0;
-        const int ns = Paper ? pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane, &rest)
-                             : append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, lane);
+        const int ns = Paper ? pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, sl_lane, &rest)
+                             : append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, sl_lane);
         if (lane == 0) {
           s_nsel = ns;
           s_floor = kf;
@@ -936,6 +940,7 @@ hipError_t loop_init_attributes() {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, k);
     if (e != hipSuccess) return e;
+    if (a.sharedSizeBytes + loop_lds_bytes(kMaxN) > (size_t)kLdsBytes) return hipErrorInvalidConfiguration;
     e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
     if (e != hipSuccess) return e;
   }
