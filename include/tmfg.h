@@ -132,7 +132,7 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream);
    last event. */
 tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
 
-/* Counters of the plan's last build (synchronous copy of 16 int32): [0] stale face
+/* Counters of the plan's last build (synchronous copy of 32 int32): [0] stale face
    recomputes, [1] walk rounds, [2] full-row sweeps, [3] selection phases, [4] walk
    batches, [5..9] microseconds spent in selection, chunk loading, walks, sweeps and
    publishing, [10] microseconds of the whole loop kernel, [11] similarities read from W
@@ -144,7 +144,11 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    maximum, [21] phases with more stale faces than one phase recomputes, [22] phases that
    loaded the most chunks one phase loads, [23] recomputed pairs that were not committed
    because a pair taken before them in heap order might change them (TMFG_RULE_PAPER),
-   [24..31] reserved. Under TMFG_RULE_PAPER, [1] counts scans for the first uninserted
+   [24] row compactions, [25..31] reserved (0). From n = 512 on, the exact and the paper
+   rule run the loop in segments: it stops after n - n/4, n - n/8, ... insertions, as long
+   as at least 128 vertices are left, and every sorted row drops its inserted entries (in
+   place, order kept) before the loop resumes; results do not depend on it. Under
+   TMFG_RULE_PAPER, [1] counts scans for the first uninserted
    entry of the corners' sorted rows instead of walk rounds. Under TMFG_RULE_CORR only these
    are kept: [0] faces recomputed because their pair vertex was inserted, [1] row scans,
    [2] extra passes (a round with more faces to recompute than one pass takes), [3] rounds,

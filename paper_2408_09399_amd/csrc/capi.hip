@@ -1,4 +1,5 @@
 // libtmfg C ABI: plans, scratch memory and the build pipeline.
+#include <climits>
 #include "../../include/tmfg.h"
 #include "common.h"
 #include "internal.h"
@@ -78,6 +79,7 @@ struct tmfg_plan_s {
   uint4* frec = nullptr;
   uint32_t* dflags = nullptr;
   int32_t* stats = nullptr;
+  uint8_t* lstate = nullptr;   // the insertion loop's state between segments
   hipEvent_t ev[kPhaseEvents] = {};
   bool timed = false;
   tmfg_batch batch = nullptr;   // the last batch built through tmfg_build_batch
@@ -96,6 +98,7 @@ void plan_free(tmfg_plan p) {
   hipFree(p->frec);
   hipFree(p->dflags);
   hipFree(p->stats);
+  hipFree(p->lstate);
   for (auto& e : p->ev)
     if (e) hipEventDestroy(e);
   if (p->batch) tmfg_batch_destroy(p->batch);
@@ -179,7 +182,8 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint
       (st = alloc((void**)&p->vals, p->sz.vals_bytes)) != TMFG_OK ||
       (st = alloc((void**)&p->scores, p->sz.scores_bytes)) != TMFG_OK ||
       (st = alloc((void**)&p->frec, p->sz.frec_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->dflags, 4)) != TMFG_OK || (st = alloc((void**)&p->stats, 128)) != TMFG_OK) {
+      (st = alloc((void**)&p->dflags, 4)) != TMFG_OK || (st = alloc((void**)&p->stats, 128)) != TMFG_OK ||
+      (st = alloc((void**)&p->lstate, tmfg::loop_state_bytes(n_max))) != TMFG_OK) {
     plan_free(p);
     return st;
   }
@@ -249,8 +253,12 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
   P.faces = job->faces;
   P.status = job->status;
   P.stats = plan->stats;
+  P.m = n - 1;
+  P.stop_at = INT_MAX;
+  P.state = plan->lstate;
   tmfg::rule_from_flags(plan->flags, &P.paper, &P.prefix);
-  TMFG_HIP(P.prefix > 0 ? tmfg::launch_corr(P, stream) : tmfg::launch_loop(P, stream));
+  TMFG_HIP(P.prefix > 0 ? tmfg::launch_corr(P, stream)
+                        : tmfg::launch_loop_compacting(P, plan->idx, plan->vals, stream));
   record(plan, 4, stream);
   plan->timed = (plan->flags & TMFG_TIMING) != 0;
   return TMFG_OK;

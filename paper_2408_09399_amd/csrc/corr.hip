@@ -177,7 +177,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
           CWork& w = work[item];
           int trips = 0;
           const uint64_t best =
-              have_cand ? paper_face<cGroup, cLoads>(P.W, P.idx, n, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
+              have_cand ? paper_face<cGroup, cLoads>(P.W, P.idx, n, n - 1, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
           if (gl == 0) {
             w.best = best;
             atomicAdd(&s_cnt[1], (unsigned long long)trips);

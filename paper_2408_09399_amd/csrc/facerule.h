@@ -131,12 +131,11 @@ __device__ __forceinline__ void seed_top4(const double* scores, int n, int* s_se
 // G * 8 * L entries at a time (L 16-byte loads of 8 ids per lane and corner, bitmap only);
 // the pair is the candidate of largest gain, ties to the lowest id (a vertex that is MaxCorrs
 // of two corners is evaluated twice, to the same key). Moves the corners' cached positions
-// forward. 0 when no vertex is left.
+// forward. 0 when no vertex is left. Rows hold m entries (n - 1, fewer once compacted).
 template <int G = kGroup, int L = 1>
-__device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* idx, int n, int ldi,
+__device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* idx, int n, int m, int ldi,
                                                const uint32_t* bits, uint16_t* ptr, int a, int b, int c, int gl,
                                                int* scans) {
-  const int m = n - 1;
   const int x3[3] = {a, b, c};
   int pos[3], cand[3];
   bool open[3];

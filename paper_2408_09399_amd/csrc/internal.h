@@ -47,10 +47,20 @@ struct LoopParams {
   int32_t* stats;          // optional, 24 counters (see tmfg_plan_stats)
   bool paper;              // the paper's face rule (Algorithm 2) instead of the exact one
   int prefix;              // > 0: corr-tmfg (Algorithm 1) with this prefix size
+  // Row compaction (single builds of the insertion loop; batches leave state null):
+  int m;                   // entries per sorted row: n - 1, or n - s once compacted at s insertions
+  int stop_at;             // save the loop's state and return once this many vertices are inserted
+  int resume;              // continue from the saved state (the rows were compacted since)
+  uint8_t* state;          // saved state, loop_state_bytes(n) bytes; null: no compaction
 };
 constexpr int kMaxPrefix = 16;   // largest corr-tmfg prefix size
 hipError_t launch_loop(const LoopParams& p, hipStream_t s);
 size_t loop_lds_bytes(int n);
+size_t loop_state_bytes(int n);
+// The insertion loop of one build in segments: between two segments every sorted row drops
+// its inserted entries (in place, order kept). idx and vals are p.idx and p.vals, writable.
+hipError_t launch_loop_compacting(LoopParams p, uint16_t* idx, float* vals, hipStream_t s);
+int loop_checkpoints(int n, int* s_out, int max);
 hipError_t launch_corr(const LoopParams& p, hipStream_t s);
 
 }  // namespace tmfg

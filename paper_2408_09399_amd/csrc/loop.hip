@@ -36,6 +36,8 @@
 // cached start (the first uninserted position: the paper's MaxCorrs pointer) forward. A
 // walk that needs more than kMaxRounds rounds is finished by a sweep of the three full
 // rows by the whole workgroup. Both give the exact best pair.
+#include <climits>
+
 #include "common.h"
 #include "facerule.h"
 #include "internal.h"
@@ -68,6 +70,19 @@ struct GroupBuf {
   float cval[3 * kCand];
 };
 
+// Saved state of a single build between two segments of its insertion loop: this header,
+// then, kStateHeader bytes in, an image of the loop's dynamic LDS (chunk maxima, inserted
+// bitmap, row positions).
+struct LoopStateHeader {
+  int live;                       // 1: a segment stopped at a checkpoint and the build goes on
+  int ins, F, since_insert;       // vertices inserted, next face id, phases since the last insertion
+  int compactions;                // checkpoints passed so far
+  unsigned long long ticks;       // loop time of the earlier segments
+  unsigned long long cnt[20];     // the loop's counters
+};
+constexpr size_t kStateHeader = 256;
+static_assert(sizeof(LoopStateHeader) <= kStateHeader, "the header fits its slot");
+
 struct Work {
   int f;            // face id
   int a, b, c;      // corners, ascending
@@ -93,7 +108,7 @@ struct Work {
 __device__ bool walk_face(const LoopParams& P, const uint32_t* bits, uint16_t* ptr, GroupBuf& gb, int a, int b,
                           int c, int gl, int gbase, uint64_t& best_out, int* rounds, int* gathers, int* skips,
                           unsigned long long* wt) {
-  const int n = P.n, m = n - 1;
+  const int n = P.n, m = P.m;
   const int ldi = (int)P.ldi;
   const int x3[3] = {a, b, c};
   const float* Wx[3] = {P.W + (size_t)a * n, P.W + (size_t)b * n, P.W + (size_t)c * n};
@@ -487,50 +502,88 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   uint16_t* ptr = (uint16_t*)(smem + LL.off_ptr);
   const int nf = 2 * n - 4;
   const uint64_t t_start = clock_ticks();
+  LoopStateHeader* hdr = (LoopStateHeader*)P.state;
+  uint64_t t_base = 0;              // loop time of earlier segments
 
-  // Errors raised by the kernels that produced W stop the build here.
-  const uint32_t fl = *P.flags;
-  if (fl) {
-    if (tid == 0) {
-      *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+  if (P.resume) {
+    // A later segment has nothing to do when the build ended or stopped in an earlier one.
+    // Every thread reads the flag before thread 0 clears it (after the first barrier below).
+    if (!hdr->live) return;
+    t_base = hdr->ticks;
+  } else {
+    if (hdr && tid == 0) hdr->live = 0;
+    // Errors raised by the kernels that produced W stop the build here.
+    const uint32_t fl = *P.flags;
+    if (fl) {
+      if (tid == 0) {
+        *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+      }
+      return;
     }
-    return;
   }
 
-  for (int i = tid; i < nf; i += kBlock) P.frec[i] = make_uint4(0, 0, 0, 0);
-  for (int i = tid; i < LL.nchunk; i += kBlock) cmax[i] = make_uint4(0, 0, 0, 0);
-  for (int i = tid; i < LL.nw; i += kBlock) bits[i] = 0;
-  for (int i = tid; i < n; i += kBlock) ptr[i] = 0;
+  if (!P.resume) {
+    for (int i = tid; i < nf; i += kBlock) P.frec[i] = make_uint4(0, 0, 0, 0);
+    for (int i = tid; i < LL.nchunk; i += kBlock) cmax[i] = make_uint4(0, 0, 0, 0);
+    for (int i = tid; i < LL.nw; i += kBlock) bits[i] = 0;
+    for (int i = tid; i < n; i += kBlock) ptr[i] = 0;
 
-  // Seed: top-4 by (score desc, id asc).
-  seed_top4<kBlock>(P.scores, n, s_seed, s_part, s_vpart);
-  if (tid == 0) {
-    const int v1 = s_seed[0], v2 = s_seed[1], v3 = s_seed[2], v4 = s_seed[3];
-    P.order[0] = v1; P.order[1] = v2; P.order[2] = v3; P.order[3] = v4;
-    const int e[12] = {v1, v2, v1, v3, v1, v4, v2, v3, v2, v4, v3, v4};
-    for (int i = 0; i < 12; ++i) P.edges[i] = e[i];
-    for (int q = 0; q < 4; ++q) bits[s_seed[q] >> 5] |= 1u << (s_seed[q] & 31);
-    const int tri[4][3] = {{v1, v2, v3}, {v1, v2, v4}, {v1, v3, v4}, {v2, v3, v4}};
-    for (int f = 0; f < 4; ++f) {
-      int x = tri[f][0], y = tri[f][1], z = tri[f][2];
-      sort3(x, y, z);
-      work[f] = Work{f, x, y, z, 0, 0};
+    // Seed: top-4 by (score desc, id asc).
+    seed_top4<kBlock>(P.scores, n, s_seed, s_part, s_vpart);
+    if (tid == 0) {
+      const int v1 = s_seed[0], v2 = s_seed[1], v3 = s_seed[2], v4 = s_seed[3];
+      P.order[0] = v1; P.order[1] = v2; P.order[2] = v3; P.order[3] = v4;
+      const int e[12] = {v1, v2, v1, v3, v1, v4, v2, v3, v2, v4, v3, v4};
+      for (int i = 0; i < 12; ++i) P.edges[i] = e[i];
+      for (int q = 0; q < 4; ++q) bits[s_seed[q] >> 5] |= 1u << (s_seed[q] & 31);
+      const int tri[4][3] = {{v1, v2, v3}, {v1, v2, v4}, {v1, v3, v4}, {v2, v3, v4}};
+      for (int f = 0; f < 4; ++f) {
+        int x = tri[f][0], y = tri[f][1], z = tri[f][2];
+        sort3(x, y, z);
+        work[f] = Work{f, x, y, z, 0, 0};
+      }
+      s_nwork = 4;
+      s_nnew = 4;
+      sel[0] = 0;
+      s_nsel = 1;
+      s_floor = ~0ull;
+      s_ins = 4;
+      s_F = 4;
+      s_stop = 0;
+      s_nsweep = 0;
+      s_bmax = 0;
+      s_next = 0;
+      if (Paper) {
+        s_best0 = 0;
+        s_unloaded = 0;
+        s_rest = 0;
+      }
     }
-    s_nwork = 4;
-    s_nnew = 4;
-    sel[0] = 0;
-    s_nsel = 1;
-    s_floor = ~0ull;
-    s_ins = 4;
-    s_F = 4;
-    s_stop = 0;
-    s_nsweep = 0;
-    s_bmax = 0;
-    s_next = 0;
-    if (Paper) {
-      s_best0 = 0;
-      s_unloaded = 0;
-      s_rest = 0;
+  } else {
+    // Resume at a phase boundary: the LDS image comes back, every row position restarts at 0
+    // (the rows were compacted since, so every entry is uninserted but the filler), and an
+    // empty phase leads to the next selection.
+    const uint32_t* img = (const uint32_t*)(P.state + kStateHeader);
+    for (int i = tid; i < (int)(LL.total / 4); i += kBlock) ((uint32_t*)smem)[i] = img[i];
+    __syncthreads();
+    for (int i = tid; i < n; i += kBlock) ptr[i] = 0;
+    if (tid == 0) {
+      s_nwork = 0;
+      s_nnew = 0;
+      s_nsel = 0;
+      s_floor = ~0ull;
+      s_ins = hdr->ins;
+      s_F = hdr->F;
+      s_stop = 0;
+      s_nsweep = 0;
+      s_bmax = 0;
+      s_next = 0;
+      if (Paper) {
+        s_best0 = 0;
+        s_unloaded = 0;
+        s_rest = 0;
+      }
+      hdr->live = 0;
     }
   }
   __syncthreads();
@@ -542,12 +595,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   //   [17] work overflows [18] chunk overflows [19] recomputed pairs not committed (paper)
   __shared__ unsigned long long s_cnt[20];
   __shared__ unsigned long long s_wt[4];         // walk sub-step ticks of group 0 (diagnostics)
-  __shared__ int s_since_insert;
+  __shared__ int s_since_insert, s_compactions;
   __shared__ unsigned long long s_t0;
-  if (tid < 20) s_cnt[tid] = 0;
+  if (tid < 20) s_cnt[tid] = P.resume ? hdr->cnt[tid] : 0;
   if (tid < 4) s_wt[tid] = 0;
   if (tid == 0) {
-    s_since_insert = 0;
+    s_since_insert = P.resume ? hdr->since_insert : 0;
+    s_compactions = P.resume ? hdr->compactions : 0;
     s_t0 = clock_ticks();
   }
   __syncthreads();
@@ -632,7 +686,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         int rw = 0, gw = 0, sw = 0;
         if (have_cand) {
           if (Paper)
-            best = paper_face(P.W, P.idx, n, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &rw);
+            best = paper_face(P.W, P.idx, n, P.m, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &rw);
           else
             ok = walk_face(P, bits, ptr, gbuf[gid], w.a, w.b, w.c, gl, gbase, best, &rw, &gw, &sw,
                            (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
@@ -725,6 +779,22 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     __syncthreads();
     TMFG_LAP(9);
     if (s_ins >= n || s_stop) break;
+    if (s_ins >= P.stop_at) {
+      // Checkpoint (single builds): save the state and return; the rows are compacted before
+      // the next segment resumes here.
+      uint32_t* img = (uint32_t*)(P.state + kStateHeader);
+      for (int i = tid; i < (int)(LL.total / 4); i += kBlock) img[i] = ((const uint32_t*)smem)[i];
+      if (tid == 0) {
+        hdr->ins = s_ins;
+        hdr->F = s_F;
+        hdr->since_insert = s_since_insert;
+        hdr->compactions = s_compactions + 1;
+        hdr->ticks = t_base + (clock_ticks() - t_start);
+        for (int i = 0; i < 20; ++i) hdr->cnt[i] = s_cnt[i];
+        hdr->live = 1;
+      }
+      return;
+    }
     // Phase A: select (wave 0).
     if (tid == 0) s_cnt[3] += 1;
     if (wave == 0) {
@@ -873,11 +943,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     if (!s_stop) *P.status = 0;
     if (P.stats) {
       for (int i = 0; i < 16; ++i) {
-        const unsigned long long v = (i == 10) ? clock_ticks() - t_start : s_cnt[i];
+        const unsigned long long v = (i == 10) ? t_base + (clock_ticks() - t_start) : s_cnt[i];
         P.stats[i] = (int32_t)(v > 0x7fffffffull ? 0x7fffffffull : v);
       }
       for (int i = 0; i < 4; ++i) P.stats[16 + i] = (int32_t)(s_wt[i] > 0x7fffffffull ? 0x7fffffffull : s_wt[i]);
       for (int i = 0; i < 4; ++i) P.stats[20 + i] = (int32_t)(s_cnt[16 + i] > 0x7fffffffull ? 0x7fffffffull : s_cnt[16 + i]);
+      P.stats[24] = s_compactions;
+      for (int i = 25; i < 32; ++i) P.stats[i] = 0;
     }
   }
 }
@@ -920,6 +992,12 @@ __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __re
     P.faces = J.faces;
     P.status = J.status;
     P.stats = nullptr;
+    P.paper = Paper;
+    P.prefix = 0;
+    P.m = J.n - 1;
+    P.stop_at = INT_MAX;
+    P.resume = 0;
+    P.state = nullptr;
     run_loop<Paper>(P, smem);
     __syncthreads();
   }
@@ -955,6 +1033,123 @@ hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, 
   else
     hipLaunchKernelGGL(batch_loop_kernel<false>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
   return hipGetLastError();
+}
+
+// Row compaction at a checkpoint of a single build, one workgroup per row (grid-stride): the
+// uninserted entries of row x keep their order and move to positions [0, cnt); positions
+// [cnt, m_new) take a filler entry (the first seed vertex, inserted from the start, with
+// similarity -inf), so every row holds m_new = n - s entries after s insertions. Entries
+// before the row's saved position are inserted, so the scan starts at its 8-aligned floor.
+// All of a pass's loads complete before the barrier of its scan and its stores land below its
+// own span, so the rows are rewritten in place. Nothing runs unless the loop stopped at a
+// checkpoint.
+constexpr int kCompactBlock = 256;
+__global__ __launch_bounds__(kCompactBlock) void compact_rows_kernel(uint16_t* __restrict__ idx,
+                                                                     float* __restrict__ vals, int n, int64_t ldi,
+                                                                     int m_old, int m_new,
+                                                                     const uint8_t* __restrict__ state,
+                                                                     const int32_t* __restrict__ order) {
+  const LoopStateHeader* hdr = (const LoopStateHeader*)state;
+  if (!hdr->live) return;
+  __shared__ uint32_t s_bits[(kMaxN + 31) / 32];
+  __shared__ int s_wsum[kCompactBlock / kWave];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const LdsLayout LL = lds_layout(n);
+  const uint8_t* img = state + kStateHeader;
+  const uint32_t* bits = (const uint32_t*)(img + LL.off_bits);
+  const uint16_t* pos0 = (const uint16_t*)(img + LL.off_ptr);
+  for (int i = tid; i < LL.nw; i += kCompactBlock) s_bits[i] = bits[i];
+  __syncthreads();
+  const uint16_t filler = (uint16_t)order[0];
+  for (int x = blockIdx.x; x < n; x += gridDim.x) {
+    uint16_t* ri = idx + (size_t)x * ldi;
+    float* rv = vals + (size_t)x * ldi;
+    int out = 0;
+    for (int base = (int)pos0[x] & ~7; base < m_old; base += kCompactBlock * 8) {
+      const int p = base + tid * 8;            // a multiple of 8 below ldi when p < m_old
+      uint4 iw = make_uint4(0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu);
+      float4 v0 = make_float4(0.f, 0.f, 0.f, 0.f), v1 = v0;
+      if (p < m_old) {
+        iw = *(const uint4*)(ri + p);
+        v0 = *(const float4*)(rv + p);
+        v1 = *(const float4*)(rv + p + 4);
+      }
+      const uint32_t wd[4] = {iw.x, iw.y, iw.z, iw.w};
+      const float vv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+      uint32_t keep = 0;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        keep |= (p + j < m_old && u < n && !is_ins(s_bits, u)) ? (1u << j) : 0u;
+      }
+      // exclusive prefix of the kept counts over the workgroup
+      const int c = __popc(keep);
+      int incl = c;
+#pragma unroll
+      for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        incl += lane >= off ? t : 0;
+      }
+      if (lane == kWave - 1) s_wsum[wave] = incl;
+      __syncthreads();
+      int before = incl - c, total = 0;
+#pragma unroll
+      for (int w = 0; w < kCompactBlock / kWave; ++w) {
+        before += w < wave ? s_wsum[w] : 0;
+        total += s_wsum[w];
+      }
+      int o = out + before;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if ((keep >> j) & 1u) {
+          ri[o] = (uint16_t)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+          rv[o] = vv[j];
+          ++o;
+        }
+      }
+      out += total;
+      __syncthreads();                         // s_wsum is reused
+    }
+    for (int q = out + tid; q < m_new; q += kCompactBlock) {
+      ri[q] = filler;
+      rv[q] = -INFINITY;
+    }
+  }
+}
+
+size_t loop_state_bytes(int n) { return kStateHeader + (lds_layout(n).total + 15) / 16 * 16; }
+
+// Inserted counts at which the rows are compacted: n - n/4, n - n/8, ... while at least
+// kCompactMinLeft vertices remain uninserted. Early in a build most of a row's leading entries
+// are uninserted and a walk finds its candidates at once; late, a walk crosses long inserted
+// stretches (whole clusters sit between a row's head and its remaining vertices), and a
+// compacted row holds only what is left.
+constexpr int kCompactMinLeft = 128;
+int loop_checkpoints(int n, int* s_out, int max) {
+  int k = 0;
+  for (int d = 4; k < max && n / d >= kCompactMinLeft; d *= 2) s_out[k++] = n - n / d;
+  return k;
+}
+
+hipError_t launch_loop_compacting(LoopParams p, uint16_t* idx, float* vals, hipStream_t s) {
+  int cp[16];
+  const int nc = p.state ? loop_checkpoints(p.n, cp, 16) : 0;
+  p.m = p.n - 1;
+  p.resume = 0;
+  p.stop_at = nc ? cp[0] : INT_MAX;
+  hipError_t e = launch_loop(p, s);
+  for (int k = 0; k < nc && e == hipSuccess; ++k) {
+    const int m_new = p.n - cp[k];
+    hipLaunchKernelGGL(compact_rows_kernel, dim3(p.n), dim3(kCompactBlock), 0, s, idx, vals, p.n, p.ldi, p.m,
+                       m_new, (const uint8_t*)p.state, (const int32_t*)p.order);
+    e = hipGetLastError();
+    if (e != hipSuccess) break;
+    p.m = m_new;
+    p.resume = 1;
+    p.stop_at = k + 1 < nc ? cp[k + 1] : INT_MAX;
+    e = launch_loop(p, s);
+  }
+  return e;
 }
 
 hipError_t launch_loop(const LoopParams& p, hipStream_t s) {

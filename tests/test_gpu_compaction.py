@@ -1,0 +1,111 @@
+"""Single builds whose insertion loop runs in segments: from n = 512 on, the loop stops at
+n - n/4, n - n/8, ... insertions (while at least 128 vertices are left), every sorted row
+drops its inserted entries in place, and the loop resumes from its saved state. The result
+must be the one-segment result bit for bit, under the exact rule and the paper's rule. These
+cases aim at what compaction could break: equal similarities (the rows' id order among ties
+must survive), rows of vertices still uninserted at a checkpoint (they carry a filler entry),
+a plan reused across builds, and a build stopped by a device error before its first
+checkpoint."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_09399_amd as tm
+from paper_2408_09399_amd import synth
+from gpu_util import to_dev, same_tmfg
+
+pytestmark = pytest.mark.gpu
+
+
+def checkpoints(n):
+    """The inserted counts at which the rows are compacted (the library's schedule)."""
+    out, d = [], 4
+    while n // d >= 128:
+        out.append(n - n // d)
+        d *= 2
+    return out
+
+
+def _build(W, plan):
+    res = tm.build(W=to_dev(W), plan=plan)
+    torch.cuda.synchronize()
+    got = res.to_numpy()
+    assert got["status"] == 0, tm.STATUS.get(got["status"])
+    assert plan.stats()[24] == len(checkpoints(W.shape[0]))     # every checkpoint was passed
+    return got
+
+
+@pytest.mark.parametrize("n", [500, 511, 512, 1000])
+def test_schedule(n):
+    """The library compacts exactly at the documented schedule (none below n = 512)."""
+    assert checkpoints(511) == [] and checkpoints(512) == [384] and checkpoints(1000) == [750]
+    _build(synth.random_symmetric(n, 12 + n), tm.Plan(n, 2))
+
+
+@pytest.mark.parametrize("n", [512, 640, 1000, 1537])
+def test_tie_heavy_exact(n):
+    W = synth.grid_symmetric(n, 4000 + n, levels=[2, 4, 8, 16][n % 4])
+    print(f"tie-heavy exact n={n}", flush=True)
+    same_tmfg(_build(W, tm.Plan(n, 2)), oracle.tmfg_lazy(W))
+
+
+@pytest.mark.parametrize("n", [512, 1000])
+def test_tie_heavy_paper_rule(n):
+    W = synth.grid_symmetric(n, 5000 + n, levels=[4, 8][n % 2])
+    print(f"tie-heavy paper rule n={n}", flush=True)
+    same_tmfg(_build(W, tm.Plan(n, 2, tm.RULE_PAPER)), oracle.tmfg_paper(W))
+
+
+@pytest.mark.parametrize("rule", ["exact", "paper"])
+def test_clusters_with_noise(rule):
+    """Clusters plus white-noise series, whose similarities sit in the middle of every row:
+    late in the build a row's remaining vertices lie behind a long inserted stretch."""
+    n, L = 1800, 256
+    sizes = [300, 500, 400, 400]
+    s = synth.planted_clusters(n, L, sizes, (0.4, 1.0), n_noise=n - sum(sizes), seed=77)
+    flags = tm.RULE_PAPER if rule == "paper" else 0
+    plan = tm.Plan(n, L, flags)
+    res = tm.build(X=to_dev(s.X), plan=plan, keep_w=True)
+    torch.cuda.synchronize()
+    got = res.to_numpy()
+    assert got["status"] == 0
+    assert plan.stats()[24] == len(checkpoints(n))
+    print(f"clusters+noise {rule}: GPU done, running the oracle", flush=True)
+    ref = oracle.tmfg_paper(got["W"]) if rule == "paper" else oracle.tmfg_lazy(got["W"])
+    same_tmfg(got, ref)
+    st = plan.stats()
+    assert st[3] >= n - 4                      # selection phases: at least one per insertion
+
+
+def test_plan_reused_across_sizes():
+    """One plan, builds of several sizes in a row (with and without checkpoints), each equal
+    to the oracle; then the first one again, byte for byte."""
+    plan = tm.Plan(1300, 2)
+    first = None
+    for k, n in enumerate([1300, 300, 777, 1300]):
+        W = synth.grid_symmetric(n, 6000 + (n if k < 3 else 1300), levels=4)
+        got = _build(W, plan)
+        if k < 3:
+            same_tmfg(got, oracle.tmfg_lazy(W))
+        blob = b"".join(np.ascontiguousarray(got[key]).tobytes() for key in ("order", "edges", "faces"))
+        if k == 0:
+            first = blob
+        if k == 3:
+            assert blob == first
+
+
+def test_device_error_stops_every_segment():
+    """A non-finite similarity stops the build at once (status 3); the later segments and
+    compactions of the same launch sequence must leave it stopped, and the plan must then
+    build a good matrix correctly."""
+    n = 900
+    plan = tm.Plan(n, 2)
+    W = synth.random_symmetric(n, 31)
+    _build(W, plan)                            # leaves the plan's saved state behind
+    bad = W.copy()
+    bad[10, 20] = bad[20, 10] = np.nan
+    res = tm.build(W=to_dev(bad), plan=plan)
+    torch.cuda.synchronize()
+    assert int(res.status.item()) == 3
+    same_tmfg(_build(W, plan), oracle.tmfg_lazy(W))
