@@ -257,8 +257,7 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
   P.stop_at = INT_MAX;
   P.state = plan->lstate;
   tmfg::rule_from_flags(plan->flags, &P.paper, &P.prefix);
-  TMFG_HIP(P.prefix > 0 ? tmfg::launch_corr(P, stream)
-                        : tmfg::launch_loop_compacting(P, plan->idx, plan->vals, stream));
+  TMFG_HIP(tmfg::launch_loop_compacting(P, plan->idx, plan->vals, stream));
   record(plan, 4, stream);
   plan->timed = (plan->flags & TMFG_TIMING) != 0;
   return TMFG_OK;

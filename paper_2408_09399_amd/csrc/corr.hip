@@ -23,6 +23,8 @@
 //   B  each work item's pair, one group of cGroup lanes per face;
 //   P  records and pair vertices are published; the chunks they touch are marked;
 //   R  the maxima of the touched chunks are rebuilt from their records.
+#include <climits>
+
 #include "common.h"
 #include "facerule.h"
 #include "internal.h"
@@ -39,6 +41,7 @@ constexpr uint16_t kNoVertex = 0xffff;
 constexpr int cGroup = 8;                        // lanes per face pair (a half row)
 constexpr int cLoads = 1;                        // 16-byte loads per lane and corner in a row scan
 static_assert(kMaxPrefix <= kWave, "the prefix fits one wave's selection");
+static_assert(kMaxPrefix <= cWaves, "one wave per chosen chunk");
 
 struct CorrLds {
   int nchunk;
@@ -65,11 +68,13 @@ struct CWork {
 
 __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   __shared__ CWork work[cMaxWork];
-  __shared__ uint4 s_lrec[kMaxPrefix];             // records of the round's kept pairs, in order
-  __shared__ int s_sel[kMaxPrefix];
+  __shared__ int s_sel[kMaxPrefix];                // the round's chunks, in key order
+  __shared__ uint64_t s_top[kMaxPrefix][kMaxPrefix];  // each chunk's best keys, in order
+  __shared__ int s_ntop[kMaxPrefix], s_nsel;
+  __shared__ uint64_t s_list[kMaxPrefix];           // the round's best keys, in order
   __shared__ uint32_t s_touch[(cMaxChunks + 31) / 32];
   __shared__ int s_tlist[cMaxChunks];
-  __shared__ int s_nwork, s_listed, s_more, s_ins, s_F, s_stop, s_next, s_ntouch, s_seed[4];
+  __shared__ int s_nwork, s_listed, s_more, s_ins, s_F, s_stop, s_next, s_ntouch, s_seed[4], s_compactions;
   __shared__ uint64_t s_part[cWaves];
   __shared__ int s_vpart[cWaves];
   // counters: [0] stale recomputes [1] row-scan trips [2] extra passes [3] rounds
@@ -88,22 +93,29 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   const int nf = 2 * n - 4;
   const int nw = (n + 31) / 32;
   const uint64_t t_start = wall_clock64();
+  LoopStateHeader* hdr = (LoopStateHeader*)P.state;
+  // entries per sorted row and the loop time of earlier segments, kept in LDS so that they
+  // hold no registers in the loop
+  __shared__ int s_m;
+  __shared__ unsigned long long s_tbase;
 
-  const uint32_t fl = *P.flags;
-  if (fl) {
-    if (tid == 0) {
-      *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+  if (P.resume) {
+    // A later segment has nothing to do when the build ended or stopped in an earlier one.
+    // Every thread reads the flag before thread 0 clears it (after a barrier below).
+    if (!hdr->live) return;
+  } else {
+    if (hdr && tid == 0) hdr->live = 0;
+    const uint32_t fl = *P.flags;
+    if (fl) {
+      if (tid == 0) {
+        *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+      }
+      return;
     }
-    return;
   }
 
-  for (int i = tid; i < nf; i += cBlock) P.frec[i] = make_uint4(0, 0, 0, 0);
-  for (int i = tid; i < LL.nchunk; i += cBlock) ckey[i] = 0;
-  for (int i = tid; i < nw; i += cBlock) bits[i] = 0;
-  for (int i = tid; i < n; i += cBlock) ptr[i] = 0;
-  for (int i = tid; i < (int)((LL.total - LL.off_fvert) / 2); i += cBlock) fvert[i] = kNoVertex;
   for (int i = tid; i < (cMaxChunks + 31) / 32; i += cBlock) s_touch[i] = 0;
-  if (tid < 9) s_cnt[tid] = 0;
+  if (tid < 9) s_cnt[tid] = P.resume ? hdr->cnt[tid] : 0;
   if (tid == 0) s_t0 = wall_clock64();
 #define CORR_LAP(slot)                    \
   if (tid == 0) {                         \
@@ -112,26 +124,58 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
     s_t0 = t1_;                           \
   }
 
-  seed_top4<cBlock>(P.scores, n, s_seed, s_part, s_vpart);
-  if (tid == 0) {
-    const int v1 = s_seed[0], v2 = s_seed[1], v3 = s_seed[2], v4 = s_seed[3];
-    P.order[0] = v1; P.order[1] = v2; P.order[2] = v3; P.order[3] = v4;
-    const int e[12] = {v1, v2, v1, v3, v1, v4, v2, v3, v2, v4, v3, v4};
-    for (int i = 0; i < 12; ++i) P.edges[i] = e[i];
-    for (int q = 0; q < 4; ++q) bits[s_seed[q] >> 5] |= 1u << (s_seed[q] & 31);
-    const int tri[4][3] = {{v1, v2, v3}, {v1, v2, v4}, {v1, v3, v4}, {v2, v3, v4}};
-    for (int f = 0; f < 4; ++f) {
-      int x = tri[f][0], y = tri[f][1], z = tri[f][2];
-      sort3(x, y, z);
-      work[f] = CWork{f, x, y, z, 0};
+  if (P.resume) {
+    // Resume at a round boundary: the LDS image comes back, every row position restarts at 0
+    // (the rows were compacted since), and a first pass that finds nothing to recompute leads
+    // to the next selection.
+    const uint32_t* img = (const uint32_t*)(P.state + kStateHeader);
+    for (int i = tid; i < (int)(LL.total / 4); i += cBlock) ((uint32_t*)smem)[i] = img[i];
+    __syncthreads();
+    for (int i = tid; i < n; i += cBlock) ptr[i] = 0;
+    if (tid == 0) {
+      s_nwork = 0;
+      s_listed = 0;
+      s_ins = hdr->ins;
+      s_F = hdr->F;
+      s_stop = 0;
+      s_more = 0;
+      s_next = 0;
+      s_compactions = hdr->compactions;
+      s_m = hdr->m_new;
+      s_tbase = hdr->ticks;
+      hdr->live = 0;
     }
-    s_nwork = 4;
-    s_listed = 4;
-    s_ins = 4;
-    s_F = 4;
-    s_stop = 0;
-    s_more = 0;
-    s_next = 0;
+    __syncthreads();
+  } else {
+    for (int i = tid; i < nf; i += cBlock) P.frec[i] = make_uint4(0, 0, 0, 0);
+    for (int i = tid; i < LL.nchunk; i += cBlock) ckey[i] = 0;
+    for (int i = tid; i < nw; i += cBlock) bits[i] = 0;
+    for (int i = tid; i < n; i += cBlock) ptr[i] = 0;
+    for (int i = tid; i < (int)((LL.total - LL.off_fvert) / 2); i += cBlock) fvert[i] = kNoVertex;
+    seed_top4<cBlock>(P.scores, n, s_seed, s_part, s_vpart);
+    if (tid == 0) {
+      const int v1 = s_seed[0], v2 = s_seed[1], v3 = s_seed[2], v4 = s_seed[3];
+      P.order[0] = v1; P.order[1] = v2; P.order[2] = v3; P.order[3] = v4;
+      const int e[12] = {v1, v2, v1, v3, v1, v4, v2, v3, v2, v4, v3, v4};
+      for (int i = 0; i < 12; ++i) P.edges[i] = e[i];
+      for (int q = 0; q < 4; ++q) bits[s_seed[q] >> 5] |= 1u << (s_seed[q] & 31);
+      const int tri[4][3] = {{v1, v2, v3}, {v1, v2, v4}, {v1, v3, v4}, {v2, v3, v4}};
+      for (int f = 0; f < 4; ++f) {
+        int x = tri[f][0], y = tri[f][1], z = tri[f][2];
+        sort3(x, y, z);
+        work[f] = CWork{f, x, y, z, 0};
+      }
+      s_nwork = 4;
+      s_listed = 4;
+      s_ins = 4;
+      s_F = 4;
+      s_stop = 0;
+      s_more = 0;
+      s_next = 0;
+      s_compactions = 0;
+      s_m = P.m;
+      s_tbase = 0;
+    }
   }
   __syncthreads();
 
@@ -177,7 +221,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
           CWork& w = work[item];
           int trips = 0;
           const uint64_t best =
-              have_cand ? paper_face<cGroup, cLoads>(P.W, P.idx, n, n - 1, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
+              have_cand ? paper_face<cGroup, cLoads>(P.W, P.idx, n, s_m, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
           if (gl == 0) {
             w.best = best;
             atomicAdd(&s_cnt[1], (unsigned long long)trips);
@@ -252,15 +296,37 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       __syncthreads();
     }
     if (s_ins >= n || s_stop) break;
+    if (s_ins >= P.stop_at) {
+      // Checkpoint (single builds): every pair names an uninserted vertex and no face is
+      // listed; save the state and return, and the rows are compacted before the next segment
+      // resumes here.
+      uint32_t* img = (uint32_t*)(P.state + kStateHeader);
+      for (int i = tid; i < (int)(LL.total / 4); i += cBlock) img[i] = ((const uint32_t*)smem)[i];
+      if (tid == 0) {
+        hdr->ins = s_ins;
+        hdr->F = s_F;
+        hdr->since_insert = 0;
+        hdr->compactions = s_compactions + 1;
+        hdr->m_old = s_m;
+        hdr->m_new = n - s_ins;
+        hdr->off_bits = (int)LL.off_bits;
+        hdr->off_ptr = (int)LL.off_ptr;
+        hdr->ticks = s_tbase + (wall_clock64() - t_start);
+        for (int i = 0; i < 9; ++i) hdr->cnt[i] = s_cnt[i];
+        hdr->live = 1;
+      }
+      return;
+    }
 
-    // ---- A: the round's prefix (wave 0)
+    // ---- A: the round's prefix
+    // A1 (wave 0): the p chunks of largest maximum, in key order. The p best pairs lie in them:
+    // a pair in any other chunk has p chunk maxima above it.
     if (wave == 0) {
       if (lane == 0) s_cnt[3] += 1;
       // the lane index is made opaque so that the chunk addresses are formed anew each round
       // rather than held in registers across the whole loop
       int sl_lane = lane;
       asm volatile("" : "+v"(sl_lane));
-      // the p chunks of largest maximum, in key order
       uint64_t ck[cChunkIters];
       uint32_t cm = 0;
 #pragma unroll
@@ -287,87 +353,93 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
         }
         ++nsel;
       }
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      // their records' keys (lane l holds record l of each chosen chunk)
-      uint64_t kk[kMaxPrefix];
-#pragma unroll
-      for (int j = 0; j < kMaxPrefix; ++j) {
-        const int f = (j < nsel ? s_sel[j] : 0) * 64 + lane;
-        kk[j] = (j < nsel && f < nf) ? rec_key(P.frec[f]) : 0;
-      }
-      // the p best keys, in order; a pair whose vertex an earlier kept pair has is dropped
-      uint64_t lk[kMaxPrefix];
-      int nl = 0;
-      for (int s = 0; s < p; ++s) {
-        uint64_t lm = 0;
-        int lj = 0;
-#pragma unroll
-        for (int j = 0; j < kMaxPrefix; ++j) {
-          const bool c = kk[j] > lm;
-          lm = c ? kk[j] : lm;
-          lj = c ? j : lj;
-        }
-        const uint64_t g = wave_max_dpp(lm);
+      if (lane == 0) s_nsel = nsel;
+    }
+    __syncthreads();
+    // A2 (one wave per chosen chunk): the chunk's p best record keys, in order. Keys are
+    // unique (they hold the face id), so one lane matches each maximum.
+    const int nsel = s_nsel;
+    if (wave < nsel) {
+      const int f = s_sel[wave] * 64 + lane;
+      uint64_t k = f < nf ? rec_key(P.frec[f]) : 0;
+      int cnt = 0;
+      for (; cnt < p; ++cnt) {
+        const uint64_t g = wave_max_dpp(k);
         if (g == 0) break;
-#pragma unroll
-        for (int j = 0; j < kMaxPrefix; ++j) kk[j] = (lm == g && j == lj) ? 0 : kk[j];
-        bool dup = false;
-#pragma unroll
-        for (int q = 0; q < kMaxPrefix; ++q) dup |= q < nl && (lk[q] & 0xffffu) == (g & 0xffffu);
-        if (!dup) {
-#pragma unroll
-          for (int q = 0; q < kMaxPrefix; ++q) lk[q] = q == nl ? g : lk[q];
-          ++nl;
+        if (lane == 0) s_top[wave][cnt] = g;
+        k = k == g ? 0 : k;
+      }
+      if (lane == 0) s_ntop[wave] = cnt;
+    }
+    __syncthreads();
+    // A3 (wave 0): merge the chunks' lists into the round's p best keys, in order; a pair
+    // whose vertex an earlier one has is dropped, and the kept pairs are applied in order,
+    // one lane each.
+    if (wave == 0) {
+      const int nt = lane < nsel ? s_ntop[lane] : 0;
+      int h = 0;
+      uint64_t head = nt > 0 ? s_top[lane][0] : 0;
+      int nlist = 0;
+      for (; nlist < p; ++nlist) {
+        const uint64_t g = wave_max_dpp(head);
+        if (g == 0) break;
+        if (lane == 0) s_list[nlist] = g;
+        if (head == g) {
+          ++h;
+          head = h < nt ? s_top[lane][h] : 0;
         }
       }
-      uint64_t mine = 0;
-#pragma unroll
-      for (int q = 0; q < kMaxPrefix; ++q) mine = q == lane ? lk[q] : mine;
-      if (lane < nl) s_lrec[lane] = P.frec[0xffff - (int)((uint32_t)mine >> 16)];
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
+      const uint64_t mine = lane < nlist ? s_list[lane] : 0;
+      const uint32_t u = (uint32_t)(mine & 0xffffu);
+      bool keep = lane < nlist;
+      for (int q = 0; q < nlist; ++q) keep = keep && !(q < lane && (uint32_t)(s_list[q] & 0xffffu) == u);
+      const uint64_t kmask = __ballot(keep);
+      const int nl = (int)__popcll(kmask);
+      const int r = (int)__popcll(kmask & ((1ull << lane) - 1));
+      const int ins0 = s_ins, F0 = s_F;
+      bool bad = false;
+      if (keep) {
+        const int f = 0xffff - (int)((uint32_t)mine >> 16);
+        const uint4 rec = P.frec[f];
+        const int x = (int)(rec.z & 0xffffu), y = (int)(rec.z >> 16), z = (int)rec.w;
+        const int ins = ins0 + r, F = F0 + 2 * r;
+        // a pair naming an inserted vertex, or more pairs than vertices left: cannot happen
+        bad = ins >= n || is_ins(bits, (int)u);
+        if (!bad) {
+          const int st = ins - 4;
+          P.order[ins] = (int)u;
+          int32_t* e = P.edges + 2 * (6 + 3 * st);
+          e[0] = (int)u; e[1] = x; e[2] = (int)u; e[3] = y; e[4] = (int)u; e[5] = z;
+          int32_t* sp = P.steps + 4 * st;
+          sp[0] = f; sp[1] = x; sp[2] = y; sp[3] = z;
+          P.step_gain[st] = unord_f32(rec.x);
+          fvert[f] = kNoVertex;
+          int t0 = (int)u, t1 = x, t2 = y;
+          sort3(t0, t1, t2);
+          work[3 * r] = CWork{f, t0, t1, t2, 0};
+          t0 = (int)u; t1 = y; t2 = z;
+          sort3(t0, t1, t2);
+          work[3 * r + 1] = CWork{F, t0, t1, t2, 0};
+          t0 = (int)u; t1 = x; t2 = z;
+          sort3(t0, t1, t2);
+          work[3 * r + 2] = CWork{F + 1, t0, t1, t2, 0};
+        }
+      }
+      const bool any_bad = __ballot(bad) != 0;
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (keep && !bad) atomicOr(&bits[u >> 5], 1u << (u & 31));
       if (lane == 0) {
-        if (nl == 0) {
+        if (nl == 0 || any_bad) {
           *P.status = 8;                   // no pair while vertices are left: cannot happen
           s_stop = 1;
         }
-        // apply the kept pairs in order
-        int ins = s_ins, F = s_F, nwk = 0;
-        for (int q = 0; q < nl; ++q) {
-          const uint4 r = s_lrec[q];
-          const int f = 0xffff - (int)(r.y >> 16), u = (int)(r.y & 0xffffu);
-          const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
-          if (ins >= n || is_ins(bits, u)) {   // a pair naming an inserted vertex: cannot happen
-            *P.status = 8;
-            s_stop = 1;
-            break;
-          }
-          bits[u >> 5] |= 1u << (u & 31);
-          const int st = ins - 4;
-          P.order[ins] = u;
-          int32_t* e = P.edges + 2 * (6 + 3 * st);
-          e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
-          int32_t* sp = P.steps + 4 * st;
-          sp[0] = f; sp[1] = x; sp[2] = y; sp[3] = z;
-          P.step_gain[st] = unord_f32(r.x);
-          fvert[f] = kNoVertex;
-          int t0 = u, t1 = x, t2 = y;
-          sort3(t0, t1, t2);
-          work[nwk++] = CWork{f, t0, t1, t2, 0};
-          t0 = u; t1 = y; t2 = z;
-          sort3(t0, t1, t2);
-          work[nwk++] = CWork{F, t0, t1, t2, 0};
-          t0 = u; t1 = x; t2 = z;
-          sort3(t0, t1, t2);
-          work[nwk++] = CWork{F + 1, t0, t1, t2, 0};
-          ++ins;
-          F += 2;
-        }
-        s_ins = ins;
-        s_F = F;
-        s_nwork = nwk;
-        s_listed = nwk;
+        s_ins = ins0 + nl;
+        s_F = F0 + 2 * nl;
+        s_nwork = 3 * nl;
+        s_listed = 3 * nl;
       }
     }
     __syncthreads();
@@ -393,8 +465,9 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       P.stats[2] = (int32_t)s_cnt[2];
       P.stats[3] = (int32_t)s_cnt[3];
       for (int i = 0; i < 5; ++i) P.stats[5 + i] = (int32_t)(s_cnt[4 + i] > 0x7fffffffull ? 0x7fffffffull : s_cnt[4 + i]);
-      const unsigned long long t = wall_clock64() - t_start;
+      const unsigned long long t = s_tbase + (wall_clock64() - t_start);
       P.stats[10] = (int32_t)(t > 0x7fffffffull ? 0x7fffffffull : t);
+      P.stats[24] = s_compactions;
     }
   }
 }
@@ -435,6 +508,10 @@ __global__ __launch_bounds__(cBlock) void batch_corr_kernel(const BatchJob* __re
     P.stats = nullptr;
     P.paper = false;
     P.prefix = prefix;
+    P.m = J.n - 1;
+    P.stop_at = INT_MAX;
+    P.resume = 0;
+    P.state = nullptr;
     run_corr(P, smem);
     __syncthreads();
   }

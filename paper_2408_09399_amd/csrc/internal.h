@@ -54,11 +54,28 @@ struct LoopParams {
   uint8_t* state;          // saved state, loop_state_bytes(n) bytes; null: no compaction
 };
 constexpr int kMaxPrefix = 16;   // largest corr-tmfg prefix size
+
+// Saved state of a single build between two segments of its loop (the lazy loop's or
+// corr-tmfg's): this header, then, kStateHeader bytes in, an image of the loop's dynamic LDS.
+struct LoopStateHeader {
+  int live;                       // 1: a segment stopped at a checkpoint and the build goes on
+  int ins, F, since_insert;       // vertices inserted, next face id, phases since the last insertion
+  int compactions;                // checkpoints passed so far
+  int m_old, m_new;               // entries per sorted row before and after the coming compaction
+  int off_bits, off_ptr;          // byte offsets of the inserted bitmap and the row positions in the image
+  unsigned long long ticks;       // loop time of the earlier segments
+  unsigned long long cnt[20];     // the loop's counters
+};
+constexpr size_t kStateHeader = 256;
+static_assert(sizeof(LoopStateHeader) <= kStateHeader, "the header fits its slot");
+
 hipError_t launch_loop(const LoopParams& p, hipStream_t s);
 size_t loop_lds_bytes(int n);
+size_t corr_lds_bytes(int n);
 size_t loop_state_bytes(int n);
-// The insertion loop of one build in segments: between two segments every sorted row drops
-// its inserted entries (in place, order kept). idx and vals are p.idx and p.vals, writable.
+// The loop of one build (the lazy loop, or corr-tmfg when p.prefix > 0) in segments: between
+// two segments every sorted row drops its inserted entries (in place, order kept). idx and
+// vals are p.idx and p.vals, writable.
 hipError_t launch_loop_compacting(LoopParams p, uint16_t* idx, float* vals, hipStream_t s);
 int loop_checkpoints(int n, int* s_out, int max);
 hipError_t launch_corr(const LoopParams& p, hipStream_t s);

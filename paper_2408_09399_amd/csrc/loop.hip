@@ -36,6 +36,7 @@
 // cached start (the first uninserted position: the paper's MaxCorrs pointer) forward. A
 // walk that needs more than kMaxRounds rounds is finished by a sweep of the three full
 // rows by the whole workgroup. Both give the exact best pair.
+#include <algorithm>
 #include <climits>
 
 #include "common.h"
@@ -70,19 +71,6 @@ struct GroupBuf {
   float cval[3 * kCand];
 };
 
-// Saved state of a single build between two segments of its insertion loop: this header,
-// then, kStateHeader bytes in, an image of the loop's dynamic LDS (chunk maxima, inserted
-// bitmap, row positions).
-struct LoopStateHeader {
-  int live;                       // 1: a segment stopped at a checkpoint and the build goes on
-  int ins, F, since_insert;       // vertices inserted, next face id, phases since the last insertion
-  int compactions;                // checkpoints passed so far
-  unsigned long long ticks;       // loop time of the earlier segments
-  unsigned long long cnt[20];     // the loop's counters
-};
-constexpr size_t kStateHeader = 256;
-static_assert(sizeof(LoopStateHeader) <= kStateHeader, "the header fits its slot");
-
 struct Work {
   int f;            // face id
   int a, b, c;      // corners, ascending
@@ -105,10 +93,10 @@ struct Work {
 // found. The code is written without data-dependent branches around loads, so each round
 // costs two dependent trips to memory (list entries, then candidate similarities), plus one
 // per skip scan. Returns false when it ran out of rounds.
-__device__ bool walk_face(const LoopParams& P, const uint32_t* bits, uint16_t* ptr, GroupBuf& gb, int a, int b,
-                          int c, int gl, int gbase, uint64_t& best_out, int* rounds, int* gathers, int* skips,
+__device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint16_t* ptr, GroupBuf& gb, int a,
+                          int b, int c, int gl, int gbase, uint64_t& best_out, int* rounds, int* gathers, int* skips,
                           unsigned long long* wt) {
-  const int n = P.n, m = P.m;
+  const int n = P.n;
   const int ldi = (int)P.ldi;
   const int x3[3] = {a, b, c};
   const float* Wx[3] = {P.W + (size_t)a * n, P.W + (size_t)b * n, P.W + (size_t)c * n};
@@ -503,13 +491,15 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   const int nf = 2 * n - 4;
   const uint64_t t_start = clock_ticks();
   LoopStateHeader* hdr = (LoopStateHeader*)P.state;
-  uint64_t t_base = 0;              // loop time of earlier segments
+  // entries per sorted row and the loop time of earlier segments, kept in LDS so that they
+  // hold no registers in the loop
+  __shared__ int s_m;
+  __shared__ unsigned long long s_tbase;
 
   if (P.resume) {
     // A later segment has nothing to do when the build ended or stopped in an earlier one.
     // Every thread reads the flag before thread 0 clears it (after the first barrier below).
     if (!hdr->live) return;
-    t_base = hdr->ticks;
   } else {
     if (hdr && tid == 0) hdr->live = 0;
     // Errors raised by the kernels that produced W stop the build here.
@@ -558,6 +548,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         s_unloaded = 0;
         s_rest = 0;
       }
+      s_m = P.m;
+      s_tbase = 0;
     }
   } else {
     // Resume at a phase boundary: the LDS image comes back, every row position restarts at 0
@@ -583,6 +575,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         s_unloaded = 0;
         s_rest = 0;
       }
+      s_m = hdr->m_new;
+      s_tbase = hdr->ticks;
       hdr->live = 0;
     }
   }
@@ -686,9 +680,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         int rw = 0, gw = 0, sw = 0;
         if (have_cand) {
           if (Paper)
-            best = paper_face(P.W, P.idx, n, P.m, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &rw);
+            best = paper_face(P.W, P.idx, n, s_m, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &rw);
           else
-            ok = walk_face(P, bits, ptr, gbuf[gid], w.a, w.b, w.c, gl, gbase, best, &rw, &gw, &sw,
+            ok = walk_face(P, s_m, bits, ptr, gbuf[gid], w.a, w.b, w.c, gl, gbase, best, &rw, &gw, &sw,
                            (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
         }
         // per-lane W reads, summed over the group
@@ -789,7 +783,11 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         hdr->F = s_F;
         hdr->since_insert = s_since_insert;
         hdr->compactions = s_compactions + 1;
-        hdr->ticks = t_base + (clock_ticks() - t_start);
+        hdr->m_old = s_m;
+        hdr->m_new = n - s_ins;
+        hdr->off_bits = (int)LL.off_bits;
+        hdr->off_ptr = (int)LL.off_ptr;
+        hdr->ticks = s_tbase + (clock_ticks() - t_start);
         for (int i = 0; i < 20; ++i) hdr->cnt[i] = s_cnt[i];
         hdr->live = 1;
       }
@@ -943,7 +941,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     if (!s_stop) *P.status = 0;
     if (P.stats) {
       for (int i = 0; i < 16; ++i) {
-        const unsigned long long v = (i == 10) ? t_base + (clock_ticks() - t_start) : s_cnt[i];
+        const unsigned long long v = (i == 10) ? s_tbase + (clock_ticks() - t_start) : s_cnt[i];
         P.stats[i] = (int32_t)(v > 0x7fffffffull ? 0x7fffffffull : v);
       }
       for (int i = 0; i < 4; ++i) P.stats[16 + i] = (int32_t)(s_wt[i] > 0x7fffffffull ? 0x7fffffffull : s_wt[i]);
@@ -1041,12 +1039,12 @@ hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, 
 // similarity -inf), so every row holds m_new = n - s entries after s insertions. Entries
 // before the row's saved position are inserted, so the scan starts at its 8-aligned floor.
 // All of a pass's loads complete before the barrier of its scan and its stores land below its
-// own span, so the rows are rewritten in place. Nothing runs unless the loop stopped at a
-// checkpoint.
+// own span, so the rows are rewritten in place. The row lengths and where the inserted bitmap
+// and the row positions sit in the saved image come from the state header; nothing runs
+// unless the loop stopped at a checkpoint.
 constexpr int kCompactBlock = 256;
 __global__ __launch_bounds__(kCompactBlock) void compact_rows_kernel(uint16_t* __restrict__ idx,
                                                                      float* __restrict__ vals, int n, int64_t ldi,
-                                                                     int m_old, int m_new,
                                                                      const uint8_t* __restrict__ state,
                                                                      const int32_t* __restrict__ order) {
   const LoopStateHeader* hdr = (const LoopStateHeader*)state;
@@ -1054,11 +1052,11 @@ __global__ __launch_bounds__(kCompactBlock) void compact_rows_kernel(uint16_t* _
   __shared__ uint32_t s_bits[(kMaxN + 31) / 32];
   __shared__ int s_wsum[kCompactBlock / kWave];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const LdsLayout LL = lds_layout(n);
+  const int m_old = hdr->m_old, m_new = hdr->m_new;
   const uint8_t* img = state + kStateHeader;
-  const uint32_t* bits = (const uint32_t*)(img + LL.off_bits);
-  const uint16_t* pos0 = (const uint16_t*)(img + LL.off_ptr);
-  for (int i = tid; i < LL.nw; i += kCompactBlock) s_bits[i] = bits[i];
+  const uint32_t* bits = (const uint32_t*)(img + hdr->off_bits);
+  const uint16_t* pos0 = (const uint16_t*)(img + hdr->off_ptr);
+  for (int i = tid; i < (n + 31) / 32; i += kCompactBlock) s_bits[i] = bits[i];
   __syncthreads();
   const uint16_t filler = (uint16_t)order[0];
   for (int x = blockIdx.x; x < n; x += gridDim.x) {
@@ -1117,13 +1115,17 @@ __global__ __launch_bounds__(kCompactBlock) void compact_rows_kernel(uint16_t* _
   }
 }
 
-size_t loop_state_bytes(int n) { return kStateHeader + (lds_layout(n).total + 15) / 16 * 16; }
+size_t loop_state_bytes(int n) {
+  const size_t img = std::max(lds_layout(n).total, corr_lds_bytes(n));
+  return kStateHeader + (img + 15) / 16 * 16;
+}
 
 // Inserted counts at which the rows are compacted: n - n/4, n - n/8, ... while at least
 // kCompactMinLeft vertices remain uninserted. Early in a build most of a row's leading entries
 // are uninserted and a walk finds its candidates at once; late, a walk crosses long inserted
 // stretches (whole clusters sit between a row's head and its remaining vertices), and a
-// compacted row holds only what is left.
+// compacted row holds only what is left. corr-tmfg inserts up to p vertices per round, so
+// it stops at the first round boundary at or past each count.
 constexpr int kCompactMinLeft = 128;
 int loop_checkpoints(int n, int* s_out, int max) {
   int k = 0;
@@ -1137,17 +1139,16 @@ hipError_t launch_loop_compacting(LoopParams p, uint16_t* idx, float* vals, hipS
   p.m = p.n - 1;
   p.resume = 0;
   p.stop_at = nc ? cp[0] : INT_MAX;
-  hipError_t e = launch_loop(p, s);
+  auto segment = [&]() { return p.prefix > 0 ? launch_corr(p, s) : launch_loop(p, s); };
+  hipError_t e = segment();
   for (int k = 0; k < nc && e == hipSuccess; ++k) {
-    const int m_new = p.n - cp[k];
-    hipLaunchKernelGGL(compact_rows_kernel, dim3(p.n), dim3(kCompactBlock), 0, s, idx, vals, p.n, p.ldi, p.m,
-                       m_new, (const uint8_t*)p.state, (const int32_t*)p.order);
+    hipLaunchKernelGGL(compact_rows_kernel, dim3(p.n), dim3(kCompactBlock), 0, s, idx, vals, p.n, p.ldi,
+                       (const uint8_t*)p.state, (const int32_t*)p.order);
     e = hipGetLastError();
     if (e != hipSuccess) break;
-    p.m = m_new;
     p.resume = 1;
     p.stop_at = k + 1 < nc ? cp[k + 1] : INT_MAX;
-    e = launch_loop(p, s);
+    e = segment();
   }
   return e;
 }

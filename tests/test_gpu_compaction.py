@@ -1,7 +1,8 @@
 """Single builds whose insertion loop runs in segments: from n = 512 on, the loop stops at
 n - n/4, n - n/8, ... insertions (while at least 128 vertices are left), every sorted row
 drops its inserted entries in place, and the loop resumes from its saved state. The result
-must be the one-segment result bit for bit, under the exact rule and the paper's rule. These
+must be the one-segment result bit for bit, under the exact rule and the paper's two rules
+(corr-tmfg stops at the first round boundary at or past each count). These
 cases aim at what compaction could break: equal similarities (the rows' id order among ties
 must survive), rows of vertices still uninserted at a checkpoint (they carry a filler entry),
 a plan reused across builds, and a build stopped by a device error before its first
@@ -57,14 +58,22 @@ def test_tie_heavy_paper_rule(n):
     same_tmfg(_build(W, tm.Plan(n, 2, tm.RULE_PAPER)), oracle.tmfg_paper(W))
 
 
-@pytest.mark.parametrize("rule", ["exact", "paper"])
+@pytest.mark.parametrize("n,p", [(512, 1), (1000, 4), (1537, 16)])
+def test_tie_heavy_corr(n, p):
+    W = synth.grid_symmetric(n, 7000 + n, levels=[4, 8, 16][p % 3])
+    print(f"tie-heavy corr n={n} p={p}", flush=True)
+    same_tmfg(_build(W, tm.Plan(n, 2, tm.rule_corr_prefix(p))), oracle.tmfg_corr_lazyrows(W, p))
+
+
+@pytest.mark.parametrize("rule", ["exact", "paper", "corr1", "corr16"])
 def test_clusters_with_noise(rule):
     """Clusters plus white-noise series, whose similarities sit in the middle of every row:
     late in the build a row's remaining vertices lie behind a long inserted stretch."""
     n, L = 1800, 256
     sizes = [300, 500, 400, 400]
     s = synth.planted_clusters(n, L, sizes, (0.4, 1.0), n_noise=n - sum(sizes), seed=77)
-    flags = tm.RULE_PAPER if rule == "paper" else 0
+    flags = {"exact": 0, "paper": tm.RULE_PAPER, "corr1": tm.rule_corr_prefix(1),
+             "corr16": tm.rule_corr_prefix(16)}[rule]
     plan = tm.Plan(n, L, flags)
     res = tm.build(X=to_dev(s.X), plan=plan, keep_w=True)
     torch.cuda.synchronize()
@@ -72,10 +81,11 @@ def test_clusters_with_noise(rule):
     assert got["status"] == 0
     assert plan.stats()[24] == len(checkpoints(n))
     print(f"clusters+noise {rule}: GPU done, running the oracle", flush=True)
-    ref = oracle.tmfg_paper(got["W"]) if rule == "paper" else oracle.tmfg_lazy(got["W"])
+    W = got["W"]
+    ref = {"exact": lambda: oracle.tmfg_lazy(W), "paper": lambda: oracle.tmfg_paper(W),
+           "corr1": lambda: oracle.tmfg_corr_lazyrows(W, 1),
+           "corr16": lambda: oracle.tmfg_corr_lazyrows(W, 16)}[rule]()
     same_tmfg(got, ref)
-    st = plan.stats()
-    assert st[3] >= n - 4                      # selection phases: at least one per insertion
 
 
 def test_plan_reused_across_sizes():
@@ -95,12 +105,13 @@ def test_plan_reused_across_sizes():
             assert blob == first
 
 
-def test_device_error_stops_every_segment():
+@pytest.mark.parametrize("flags", [0, 1], ids=["exact", "corr4"])
+def test_device_error_stops_every_segment(flags):
     """A non-finite similarity stops the build at once (status 3); the later segments and
     compactions of the same launch sequence must leave it stopped, and the plan must then
     build a good matrix correctly."""
     n = 900
-    plan = tm.Plan(n, 2)
+    plan = tm.Plan(n, 2, tm.rule_corr_prefix(4) if flags else 0)
     W = synth.random_symmetric(n, 31)
     _build(W, plan)                            # leaves the plan's saved state behind
     bad = W.copy()
@@ -108,4 +119,4 @@ def test_device_error_stops_every_segment():
     res = tm.build(W=to_dev(bad), plan=plan)
     torch.cuda.synchronize()
     assert int(res.status.item()) == 3
-    same_tmfg(_build(W, plan), oracle.tmfg_lazy(W))
+    same_tmfg(_build(W, plan), oracle.tmfg_corr_lazyrows(W, 4) if flags else oracle.tmfg_lazy(W))
