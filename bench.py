@@ -77,9 +77,10 @@ def source_digest(kernel: str) -> str:
 
 
 def measured_traffic(kernel: str, config: str):
-    """HBM bytes per launch of `kernel` on `config` from the committed counter summary
-    (FETCH_SIZE and WRITE_SIZE per dispatch, each scaled by what the same counter read for a
-    copy of known size), or None when there is none or the kernel's source has changed since."""
+    """HBM bytes per build of `kernel` on `config` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE summed over the build's launches of the kernel, each scaled by
+    what the same counter read for a copy of known size), or None when there is none or the
+    kernel's source has changed since."""
     path = os.path.join(HERE, "profiles", f"{kernel}_{config}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -92,8 +93,8 @@ def measured_traffic(kernel: str, config: str):
     try:
         if kv["source_sha256_16"] != source_digest(kernel):
             return None
-        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_scale"])
-        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_scale"])
+        fetch = float(kv["fetch_kib_per_build"]) * float(kv["fetch_scale"])
+        write = float(kv["write_kib_per_build"]) * float(kv["write_scale"])
     except (KeyError, ValueError):
         return None
     return (fetch + write) * 1024.0
@@ -574,6 +575,10 @@ def main():
     traffic = measured_traffic(dom, args.config)
     roofline = {"kernel": dom, "bound": b, "achieved": round(ach, 3), "peak": peak, "unit": unit,
                 "frac": round(ach / peak, 5), "traffic": None if traffic is None else round(traffic)}
+    if dom == "tmfg_loop":
+        # a build runs the loop kernel in stats[24] + 1 launches with row compactions between;
+        # achieved and traffic count the whole build (all launches)
+        roofline["per"] = f"build ({stats[24] + 1} launches, {stats[24]} row compactions between)"
 
     out = {
         "metric": "TMFG insertions/s at n=20k; batched builds/s; p50/p99 latency at fixed QPS",
@@ -596,6 +601,7 @@ def main():
                        "critical_rounds": stats[12], "walks_ge4": stats[13], "walks_ge16": stats[14],
                        "skip_scans": stats[15], "stale_top_phases": stats[20],
                        "work_overflow_phases": stats[21], "chunk_overflow_phases": stats[22],
+                       "row_compactions": stats[24],
                        "us": {"select": stats[5], "load": stats[6], "walk": stats[7],
                               "sweep": stats[8], "publish": stats[9], "kernel": stats[10]}},
         "roofline": roofline,

@@ -147,7 +147,8 @@ size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags) {
   (void)flags;
   if (n_max < tmfg::kMinN) return 0;
   const Sizes s = sizes_for(n_max, L_max);
-  return s.z_bytes + s.w_bytes + s.idx_bytes + s.vals_bytes + s.scores_bytes + s.frec_bytes + 256 * 2;
+  return s.z_bytes + s.w_bytes + s.idx_bytes + s.vals_bytes + s.scores_bytes + s.frec_bytes + 256 * 2 +
+         tmfg::loop_state_bytes(n_max);
 }
 
 tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags) {
