@@ -606,6 +606,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     s_t0 = t1_;                           \
   }
   for (;;) {
+    // The thread index is made opaque each phase, so that the many LDS addresses derived from
+    // it are formed anew rather than held (and spilled) across the loop.
+    int tid_o = tid;
+    asm volatile("" : "+v"(tid_o));
+    const int tid = tid_o, lane = tid & 63, wave = tid >> 6;
+    const int gl = lane & (kGroup - 1), gbase = lane & ~(kGroup - 1);
+    const int gid = tid / kGroup;
     // Phase B0: load the records of the queued chunks (one wave per chunk, one record per
     // lane). Each record is linked to the work item that will replace it: a new face, or a
     // stale record ranked above the floor, which is queued for recomputation.
