@@ -42,15 +42,24 @@ __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
 }
 __device__ __forceinline__ uint64_t max64(uint64_t a, uint64_t b) { return a > b ? a : b; }
 
-// The same over groups of G = 4, 8 or 16 lanes (quads, half rows, rows).
+// The same over groups of G = 4, 8 or 16 lanes (quads, half rows, rows). A 64-bit maximum
+// is taken as two 32-bit ones: the high words, then the low words of the lanes whose high
+// word is that maximum (0, the identity, elsewhere); each step is one DPP max.
+template <int G>
+__device__ __forceinline__ uint32_t group_max_u32(uint32_t x) {
+  static_assert(G == 4 || G == 8 || G == 16, "a group is a quad, a half row or a row");
+  x = max(x, dpp32<kDppXor1>(x));
+  x = max(x, dpp32<kDppXor2>(x));
+  if (G >= 8) x = max(x, dpp32<kDppHalfMirror>(x));
+  if (G >= 16) x = max(x, dpp32<kDppMirror>(x));
+  return x;
+}
 template <int G>
 __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) {
-  static_assert(G == 4 || G == 8 || G == 16, "a group is a quad, a half row or a row");
-  v = max64(v, dpp64<kDppXor1>(v));
-  v = max64(v, dpp64<kDppXor2>(v));
-  if (G >= 8) v = max64(v, dpp64<kDppHalfMirror>(v));
-  if (G >= 16) v = max64(v, dpp64<kDppMirror>(v));
-  return v;
+  const uint32_t vh = (uint32_t)(v >> 32);
+  const uint32_t hi = group_max_u32<G>(vh);
+  const uint32_t lo = group_max_u32<G>(vh == hi ? (uint32_t)v : 0u);
+  return ((uint64_t)hi << 32) | lo;
 }
 template <int G>
 __device__ __forceinline__ int group_min_i32(int x) {
@@ -64,17 +73,20 @@ __device__ __forceinline__ int group_min_i32(int x) {
 __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) { return group_max_u64<kGroup>(v); }
 __device__ __forceinline__ int group_min_i32(int x) { return group_min_i32<kGroup>(x); }
 
-// Wave-wide maximum: row maxima by DPP, then the four rows read out lane by lane.
-__device__ __forceinline__ uint64_t wave_max_dpp(uint64_t v) {
-  v = group_max_u64(v);
-  uint64_t m = 0;
+// Wave-wide maximum: row maxima by DPP, then the four rows read out lane by lane; for 64
+// bits, the high words first, then the low words of the lanes that hold the high maximum.
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+  x = group_max_u32<16>(x);
+  uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)x, 0);
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 16 * r);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 16 * r);
-    m = max64(m, ((uint64_t)hi << 32) | lo);
-  }
+  for (int r = 1; r < 4; ++r) m = max(m, (uint32_t)__builtin_amdgcn_readlane((int)x, 16 * r));
   return m;
+}
+__device__ __forceinline__ uint64_t wave_max_dpp(uint64_t v) {
+  const uint32_t vh = (uint32_t)(v >> 32);
+  const uint32_t hi = wave_max_u32(vh);
+  const uint32_t lo = wave_max_u32(vh == hi ? (uint32_t)v : 0u);
+  return ((uint64_t)hi << 32) | lo;
 }
 
 // Seed (Algorithm 1 and Algorithm 2, first comment): the four vertices of largest score,
