@@ -52,6 +52,7 @@ constexpr int kGroups = kBlock / kGroup;         // face walks in flight
 constexpr int kScan = 4;                         // list entries per lane and round
 constexpr int kSpan = kScan * kGroup;            // list positions scanned per round
 constexpr int kCand = 8;                         // candidates taken per list and round
+constexpr int kSlots = (3 * kCand + kGroup - 1) / kGroup;   // staged candidates per lane
 constexpr int kSkipLoads = 4;                    // 16-byte loads per lane in a skip scan
 constexpr int kMaxRounds = 64;
 constexpr int kMaxWork = 256;                    // faces recomputed per selection phase
@@ -182,13 +183,13 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     TMFG_WT(0);
-    // (3) evaluate the staged candidates, two slots per lane; the two similarities not
+    // (3) evaluate the staged candidates, kSlots per lane (two at kCand = 8); the two similarities not
     //     carried by the list are read from W, all loads issued before any is used
-    int su[2], st[2];
-    float sv[2], sw[2][2];
-    bool sok[2];
+    int su[kSlots], st[kSlots];
+    float sv[kSlots], sw[kSlots][2];
+    bool sok[kSlots];
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kSlots; ++e) {
       const int sl = gl + e * kGroup;
       const int t = sl / kCand;
       st[e] = t;
@@ -197,7 +198,7 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       sv[e] = sok[e] ? gb.cval[sl] : 0.0f;
     }
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kSlots; ++e) {
       const int t = st[e];
       const float* o1 = t == 0 ? Wx[1] : Wx[0];
       const float* o2 = t == 2 ? Wx[1] : Wx[2];
@@ -206,7 +207,7 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     }
     uint64_t k = 0;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < kSlots; ++e) {
       const int t = st[e];
       float w0, w1, w2;
       if (t == 0) { w0 = sv[e]; w1 = sw[e][0]; w2 = sw[e][1]; }
