@@ -113,7 +113,9 @@ typedef struct {
 
 /* Create a plan for builds with n <= n_max and L <= L_max on the current HIP device.
    Allocates the scratch (similarity matrix, standardised series, sorted ids, face
-   records; see tmfg_footprint_bytes). */
+   records, the insertion loop's saved state; see tmfg_footprint_bytes). A plan serves one
+   build at a time: builds on one plan must be ordered (the same stream, or events), since
+   each one rewrites all of the plan's scratch. */
 tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags);
 
 /* Release a plan and its scratch. Waits for the plan's outstanding work. NULL is a no-op. */
