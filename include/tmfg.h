@@ -181,7 +181,8 @@ tmfg_status tmfg_batch_destroy(tmfg_batch batch);
    timing each knob on the batch's inputs at creation; those inputs must then be valid):
    [0..7] sort configuration index of each size class (-1: class absent), [8] rows per sort
    workgroup (0: one resident fill of the device), [9] persistent loop workgroups,
-   [10] configurations timed, [11] milliseconds spent tuning, [12..15] reserved. The
+   [10] configurations timed, [11] milliseconds spent tuning, [12] walk rounds before a
+   face is swept instead (64 untuned; 64, 16 or 8 tuned), [13..15] reserved. The
    configuration never changes results. */
 tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]);
 

@@ -366,7 +366,7 @@ class Batch:
         _check(_lib().tmfg_batch_config(self._h, out), "tmfg_batch_config")
         v = list(out)
         return {"sort_config": v[0:8], "sort_rows_per_wg": v[8], "loop_workgroups": v[9],
-                "tune_trials": v[10], "tune_ms": v[11]}
+                "tune_trials": v[10], "tune_ms": v[11], "walk_rounds": v[12]}
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

@@ -190,7 +190,8 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
     if ((e = batch_enqueue_sort(spec, L, c, s)) != hipSuccess) return e;
   if (spec.prefix > 0)
     return launch_batch_corr(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.prefix, s);
-  return launch_batch_loop(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper, s);
+  return launch_batch_loop(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper,
+                           L.max_rounds, s);
 }
 
 hipError_t batch_enqueue_sort(const BatchSpec& spec, const BatchLaunch& L, int cls, hipStream_t s) {
@@ -207,7 +208,8 @@ hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipSt
   if (spec.prefix > 0)
     return launch_batch_corr(L.d_jobs, L.d_ints + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max,
                              spec.prefix, s);
-  return launch_batch_loop(L.d_jobs, L.d_ints + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper, s);
+  return launch_batch_loop(L.d_jobs, L.d_ints + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper,
+                           L.max_rounds, s);
 }
 
 hipError_t batch_grid(int device, int count, int n_max, bool paper, int prefix, int* grid) {
@@ -278,7 +280,8 @@ hipError_t time_best(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, F e
 // when it is at least 2% faster:
 //   * the launch configuration (threads x slots per thread) of each size class's row sort;
 //   * the rows each sort workgroup takes (resident fill of the device, or 2, 4, 16 rows);
-//   * the number of persistent loop workgroups (all that fit, three quarters, half).
+//   * the number of persistent loop workgroups (all that fit, three quarters, half);
+//   * the walk rounds after which a face is swept instead (64, 16, 8; exact rule only).
 // Results do not depend on any of these.
 hipError_t autotune(tmfg_batch b) {
   tmfg::BatchLaunch& L = b->launch;
@@ -339,6 +342,15 @@ hipError_t autotune(tmfg_batch b) {
       ++b->tune_trials;
       if (t < 0.98f * best) best = t;
       else L.grid = keep;
+    }
+    for (int r : {16, 8}) {
+      if (S.prefix > 0 || S.paper) break;      // only the exact rule walks
+      const int keep = L.max_rounds;
+      L.max_rounds = r;
+      if ((e = time_best(st, e0, e1, 2, loops, &t)) != hipSuccess) goto done;
+      ++b->tune_trials;
+      if (t < 0.98f * best) best = t;
+      else L.max_rounds = keep;
     }
   }
   if ((e = hipEventRecord(eb, st)) != hipSuccess || (e = hipEventSynchronize(eb)) != hipSuccess) goto done;
@@ -477,6 +489,7 @@ tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]) {
   out[9] = batch->launch.grid;
   out[10] = batch->tune_trials;
   out[11] = (int32_t)(batch->tune_ms + 0.5f);
+  out[12] = batch->launch.max_rounds;
   return TMFG_OK;
 }
 

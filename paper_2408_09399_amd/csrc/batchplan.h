@@ -48,6 +48,7 @@ struct BatchLaunch {
   int grid = 1;                                             // persistent loop workgroups
   int sort_cfg[kSortClasses] = {-1, -1, -1, -1, -1, -1, -1, -1};   // -1: the class default
   int sort_rows = 0;                                        // rows per sort workgroup (0: resident fill)
+  int max_rounds = kWalkRounds;                             // walk rounds before the full-row sweep
   std::vector<std::pair<const float*, float*>> w_copies;    // caller W -> W_out
   std::vector<size_t> w_copy_bytes;
 };

@@ -257,6 +257,7 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
   P.m = n - 1;
   P.stop_at = INT_MAX;
   P.state = plan->lstate;
+  P.max_rounds = tmfg::kWalkRounds;
   tmfg::rule_from_flags(plan->flags, &P.paper, &P.prefix);
   TMFG_HIP(tmfg::launch_loop_compacting(P, plan->idx, plan->vals, stream));
   record(plan, 4, stream);

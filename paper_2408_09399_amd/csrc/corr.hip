@@ -512,6 +512,7 @@ __global__ __launch_bounds__(cBlock) void batch_corr_kernel(const BatchJob* __re
     P.stop_at = INT_MAX;
     P.resume = 0;
     P.state = nullptr;
+    P.max_rounds = kWalkRounds;
     run_corr(P, smem);
     __syncthreads();
   }

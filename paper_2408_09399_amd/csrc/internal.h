@@ -52,7 +52,9 @@ struct LoopParams {
   int stop_at;             // save the loop's state and return once this many vertices are inserted
   int resume;              // continue from the saved state (the rows were compacted since)
   uint8_t* state;          // saved state, loop_state_bytes(n) bytes; null: no compaction
+  int max_rounds;          // walk rounds before a walk gives up and its face is swept (exact either way)
 };
+constexpr int kWalkRounds = 64;   // the round limit of single builds and of untuned batches
 constexpr int kMaxPrefix = 16;   // largest corr-tmfg prefix size
 
 // Saved state of a single build between two segments of its loop (the lazy loop's or
@@ -130,7 +132,7 @@ bool sort_config_fits(int cfg, int cls);
 // Persistent insertion loops: `grid` workgroups take instances from `order` (device array
 // of job indices, largest first) through the counter at *queue_head.
 hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
-                             int n_max, bool paper, hipStream_t s);
+                             int n_max, bool paper, int max_rounds, hipStream_t s);
 hipError_t launch_batch_corr(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
                              int n_max, int prefix, hipStream_t s);
 int corr_tiles(int n);                        // upper-triangular correlation tiles of n rows

@@ -34,8 +34,9 @@
 // T = (A + B) + C of those values (float32 addition is monotone). The walk stops when the
 // best gain seen is strictly above T, or a list is used up. Every walk moves each list's
 // cached start (the first uninserted position: the paper's MaxCorrs pointer) forward. A
-// walk that needs more than kMaxRounds rounds is finished by a sweep of the three full
-// rows by the whole workgroup. Both give the exact best pair.
+// walk that needs more than its round limit (64 unless a batch's autotuner picks another)
+// is finished by a sweep of the three full rows by the whole workgroup. Both give the
+// exact best pair.
 #include <algorithm>
 #include <climits>
 
@@ -54,7 +55,6 @@ constexpr int kSpan = kScan * kGroup;            // list positions scanned per r
 constexpr int kCand = 8;                         // candidates taken per list and round
 constexpr int kSlots = (3 * kCand + kGroup - 1) / kGroup;   // staged candidates per lane
 constexpr int kSkipLoads = 4;                    // 16-byte loads per lane in a skip scan
-constexpr int kMaxRounds = 64;
 constexpr int kMaxWork = 256;                    // faces recomputed per selection phase
 constexpr int kMaxSel = 48;                      // chunks loaded per selection phase
 constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
@@ -123,7 +123,7 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     tw = c_;                                                        \
   }
   uint64_t tw = wt ? wall_clock64() : 0;
-  for (; r < kMaxRounds && !done; ++r) {
+  for (; r < P.max_rounds && !done; ++r) {
     // (1) this round's span of every list: ids and similarities (addresses kept inside
     //     the row; entries at or past m are masked below)
     int q[3];
@@ -972,7 +972,7 @@ __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
 template <bool Paper>
 __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __restrict__ jobs,
                                                             const int* __restrict__ order, int count,
-                                                            int* __restrict__ queue_head) {
+                                                            int* __restrict__ queue_head, int max_rounds) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
   __shared__ int s_job;
   for (;;) {
@@ -1004,6 +1004,7 @@ __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __re
     P.stop_at = INT_MAX;
     P.resume = 0;
     P.state = nullptr;
+    P.max_rounds = max_rounds;
     run_loop<Paper>(P, smem);
     __syncthreads();
   }
@@ -1032,12 +1033,14 @@ hipError_t loop_init_attributes() {
 }
 
 hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
-                             int n_max, bool paper, hipStream_t s) {
+                             int n_max, bool paper, int max_rounds, hipStream_t s) {
   const size_t lds = loop_lds_bytes(n_max);
   if (paper)
-    hipLaunchKernelGGL(batch_loop_kernel<true>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
+    hipLaunchKernelGGL(batch_loop_kernel<true>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head,
+                       max_rounds);
   else
-    hipLaunchKernelGGL(batch_loop_kernel<false>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head);
+    hipLaunchKernelGGL(batch_loop_kernel<false>, dim3(grid), dim3(kBlock), lds, s, jobs, order, count, queue_head,
+                       max_rounds);
   return hipGetLastError();
 }
 

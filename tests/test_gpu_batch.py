@@ -113,6 +113,7 @@ def test_autotuned_batch_same_results():
     cfg = tuned.config()
     assert cfg["tune_trials"] > 0 and cfg["loop_workgroups"] >= 1
     assert any(c >= 0 for c in cfg["sort_config"])
+    assert cfg["walk_rounds"] in (64, 16, 8)
     for rep in range(2):
         got = [r.to_numpy() for r in tuned.run()]
         torch.cuda.synchronize()
@@ -120,6 +121,6 @@ def test_autotuned_batch_same_results():
             assert g["status"] == 0
             same_tmfg(g, w)
     base = ref.config()
-    assert base["tune_trials"] == 0
+    assert base["tune_trials"] == 0 and base["walk_rounds"] == 64
     ref.close()
     tuned.close()
