@@ -82,6 +82,13 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
   for (int r = 1; r < 4; ++r) m = max(m, (uint32_t)__builtin_amdgcn_readlane((int)x, 16 * r));
   return m;
 }
+__device__ __forceinline__ int wave_min_i32(int x) {
+  x = group_min_i32<16>(x);
+  int m = __builtin_amdgcn_readlane(x, 0);
+#pragma unroll
+  for (int r = 1; r < 4; ++r) m = min(m, __builtin_amdgcn_readlane(x, 16 * r));
+  return m;
+}
 __device__ __forceinline__ uint64_t wave_max_dpp(uint64_t v) {
   const uint32_t vh = (uint32_t)(v >> 32);
   const uint32_t hi = wave_max_u32(vh);

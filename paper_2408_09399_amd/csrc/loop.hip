@@ -473,6 +473,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ uint4 s_crec[kMaxSel][kWave];       // the loaded chunk records
   __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
+  __shared__ int s_u;                            // the vertex the last selection inserted
   __shared__ uint64_t s_floor;
   // paper rule: old keys and new keys of the work items, the best fresh record of the loaded
   // chunks that stays, and the best stale record that was not recomputed
@@ -661,6 +662,42 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       }
       s_crec[sl][lane] = crec;
       s_link[sl][lane] = (int16_t)link;
+    }
+    // The three new faces share the new vertex u, whose row no walk has read (a vertex is a
+    // face corner only once inserted), so its position is 0 while its most similar vertices
+    // (its cluster) are mostly inserted already. The last wave, which has no chunk to load
+    // unless nearly every wave does, moves that position to u's first uninserted entry now,
+    // 512 entries per trip, so that the new faces' walks, usually the deepest of the phase,
+    // start there instead of each crossing the same stretch.
+    if (nnew == 3 && s_ins < n && wave == kWaves - 1) {
+      const int u = s_u;
+      const uint16_t* row = P.idx + (size_t)u * P.ldi;
+      const int ldi = (int)P.ldi;
+      int p = ptr[u];
+      for (;;) {
+        const int qs = (p & ~7) + lane * 8;
+        const uint4 sv = *(const uint4*)(row + min(qs, ldi - 8));
+        const uint32_t wd[4] = {sv.x, sv.y, sv.z, sv.w};
+        int fp = 0x7fffffff;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int id = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+          const int q = qs + j;
+          const bool ok = q >= p && q < s_m && !is_ins(bits, id < n ? id : 0);
+          fp = ok ? min(fp, q) : fp;
+        }
+        const int f = wave_min_i32(fp);
+        if (f != 0x7fffffff) {
+          p = f;
+          break;
+        }
+        p = (p & ~7) + kWave * 8;
+        if (p >= s_m) {
+          p = s_m;
+          break;
+        }
+      }
+      if (lane == 0 && p > (int)ptr[u]) ptr[u] = (uint16_t)p;
     }
     __syncthreads();
     TMFG_LAP(6);
@@ -859,6 +896,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           sort3(t0_, t1_, t2_);
           work[2] = Work{F + 1, t0_, t1_, t2_, 0, 0};
           s_ins = ins + 1;
+          s_u = u;
           s_F = F + 2;
           s_nwork = 3;
           s_nnew = 3;
