@@ -71,6 +71,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   __shared__ int s_sel[kMaxPrefix];                // the round's chunks, in key order
   __shared__ uint64_t s_top[kMaxPrefix][kMaxPrefix];  // each chunk's best keys, in order
   __shared__ int s_ntop[kMaxPrefix], s_nsel;
+  __shared__ int s_newu[kMaxPrefix], s_nnewu;        // the vertices the last round inserted
   __shared__ uint64_t s_list[kMaxPrefix];           // the round's best keys, in order
   __shared__ uint32_t s_touch[(cMaxChunks + 31) / 32];
   __shared__ int s_tlist[cMaxChunks];
@@ -141,6 +142,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       s_more = 0;
       s_next = 0;
       s_compactions = hdr->compactions;
+      s_nnewu = 0;
       s_m = hdr->m_new;
       s_tbase = hdr->ticks;
       hdr->live = 0;
@@ -173,6 +175,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       s_more = 0;
       s_next = 0;
       s_compactions = 0;
+      s_nnewu = 0;
       s_m = P.m;
       s_tbase = 0;
     }
@@ -184,6 +187,41 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
     // ---- passes: the listed faces and every face whose pair vertex is inserted
     for (int pass = 0;; ++pass) {
       if (have_cand) {
+        // The new faces of the round's vertices search those vertices' rows, which no pair
+        // search has read (a vertex is a face corner only once inserted): their positions
+        // are 0 while their most similar vertices are mostly inserted. In the first pass one
+        // wave per new vertex moves its position to the first uninserted entry, 512 entries
+        // per trip, beside the scan below.
+        if (pass == 0 && wave < s_nnewu) {
+          const int u = s_newu[wave];
+          const uint16_t* row = P.idx + (size_t)u * P.ldi;
+          const int ldi = (int)P.ldi, mr = s_m;
+          int pu = ptr[u];
+          for (;;) {
+            const int qs = (pu & ~7) + lane * 8;
+            const uint4 sv = *(const uint4*)(row + min(qs, ldi - 8));
+            const uint32_t wd[4] = {sv.x, sv.y, sv.z, sv.w};
+            int fp = 0x7fffffff;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              const int id = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+              const int q = qs + j;
+              const bool ok = q >= pu && q < mr && !is_ins(bits, id < n ? id : 0);
+              fp = ok ? min(fp, q) : fp;
+            }
+            const int f = wave_min_i32(fp);
+            if (f != 0x7fffffff) {
+              pu = f;
+              break;
+            }
+            pu = (pu & ~7) + kWave * 8;
+            if (pu >= mr) {
+              pu = mr;
+              break;
+            }
+          }
+          if (lane == 0 && pu > (int)ptr[u]) ptr[u] = (uint16_t)pu;
+        }
         // S: pair vertices, eight per 16-byte read; the matching faces' corners come from
         // their records
         const int F = s_F;
@@ -430,8 +468,12 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       const bool any_bad = __ballot(bad) != 0;
       __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
       __builtin_amdgcn_wave_barrier();
-      if (keep && !bad) atomicOr(&bits[u >> 5], 1u << (u & 31));
+      if (keep && !bad) {
+        atomicOr(&bits[u >> 5], 1u << (u & 31));
+        s_newu[r] = (int)u;
+      }
       if (lane == 0) {
+        s_nnewu = any_bad ? 0 : nl;
         if (nl == 0 || any_bad) {
           *P.status = 8;                   // no pair while vertices are left: cannot happen
           s_stop = 1;
