@@ -473,7 +473,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ uint4 s_crec[kMaxSel][kWave];       // the loaded chunk records
   __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
-  __shared__ int s_u;                            // the vertex the last selection inserted
+  __shared__ int s_u4[4];                        // the vertex the last selection inserted, and the
+                                                 // corners of the face it split
   __shared__ uint64_t s_floor;
   // paper rule: old keys and new keys of the work items, the best fresh record of the loaded
   // chunks that stays, and the best stale record that was not recomputed
@@ -668,9 +669,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // (its cluster) are mostly inserted already. The last wave, which has no chunk to load
     // unless nearly every wave does, moves that position to u's first uninserted entry now,
     // 512 entries per trip, so that the new faces' walks, usually the deepest of the phase,
-    // start there instead of each crossing the same stretch.
-    if (nnew == 3 && s_ins < n && wave == kWaves - 1) {
-      const int u = s_u;
+    // start there instead of each crossing the same stretch. The three waves before it do
+    // the same for the split face's corners, the new faces' other lists.
+    if (nnew == 3 && s_ins < n && wave >= kWaves - 4) {
+      const int u = s_u4[kWaves - 1 - wave];
       const uint16_t* row = P.idx + (size_t)u * P.ldi;
       const int ldi = (int)P.ldi;
       int p = ptr[u];
@@ -896,7 +898,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           sort3(t0_, t1_, t2_);
           work[2] = Work{F + 1, t0_, t1_, t2_, 0, 0};
           s_ins = ins + 1;
-          s_u = u;
+          s_u4[0] = u;
+          s_u4[1] = x;
+          s_u4[2] = y;
+          s_u4[3] = z;
           s_F = F + 2;
           s_nwork = 3;
           s_nnew = 3;
