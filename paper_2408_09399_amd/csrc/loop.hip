@@ -449,6 +449,38 @@ __device__ int pick_top_stale_chunks(const uint32_t (&khi)[kChunkIters], const u
 }
 static_assert(kPaperChunks + 2 <= kMaxSel, "the paper rule's chunks fit the load list");
 
+// Wave: move vertex v's row position to its first uninserted entry, 512 entries per trip
+// (entries before the position are inserted; the position only grows).
+__device__ __forceinline__ void advance_row(const uint16_t* __restrict__ idx, int ldi, const uint32_t* bits,
+                                            uint16_t* ptr, int v, int m, int n, int lane) {
+  const uint16_t* row = idx + (size_t)v * ldi;
+  int p = ptr[v];
+  for (;;) {
+    const int qs = (p & ~7) + lane * 8;
+    const uint4 sv = *(const uint4*)(row + min(qs, ldi - 8));
+    const uint32_t wd[4] = {sv.x, sv.y, sv.z, sv.w};
+    int fp = 0x7fffffff;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int id = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+      const int q = qs + j;
+      const bool ok = q >= p && q < m && !is_ins(bits, id < n ? id : 0);
+      fp = ok ? min(fp, q) : fp;
+    }
+    const int f = wave_min_i32(fp);
+    if (f != 0x7fffffff) {
+      p = f;
+      break;
+    }
+    p = (p & ~7) + kWave * 8;
+    if (p >= m) {
+      p = m;
+      break;
+    }
+  }
+  if (lane == 0 && p > (int)ptr[v]) ptr[v] = (uint16_t)p;
+}
+
 // The record a work item publishes, as one sortable key (0 when it has no vertex).
 __device__ __forceinline__ uint64_t work_key(const Work& w) { return rec_key(make_rec(w)); }
 
@@ -475,6 +507,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
   __shared__ int s_u4[4];                        // the vertex the last selection inserted, and the
                                                  // corners of the face it split
+  __shared__ int s_adv;                          // selection's word to the advancing waves: 0 not yet,
+                                                 // 1 advance s_u4's rows, 2 nothing to advance
   __shared__ uint64_t s_floor;
   // paper rule: old keys and new keys of the work items, the best fresh record of the loaded
   // chunks that stays, and the best stale record that was not recomputed
@@ -664,43 +698,6 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_crec[sl][lane] = crec;
       s_link[sl][lane] = (int16_t)link;
     }
-    // The three new faces share the new vertex u, whose row no walk has read (a vertex is a
-    // face corner only once inserted), so its position is 0 while its most similar vertices
-    // (its cluster) are mostly inserted already. The last wave, which has no chunk to load
-    // unless nearly every wave does, moves that position to u's first uninserted entry now,
-    // 512 entries per trip, so that the new faces' walks, usually the deepest of the phase,
-    // start there instead of each crossing the same stretch. The three waves before it do
-    // the same for the split face's corners, the new faces' other lists.
-    if (nnew == 3 && s_ins < n && wave >= kWaves - 4) {
-      const int u = s_u4[kWaves - 1 - wave];
-      const uint16_t* row = P.idx + (size_t)u * P.ldi;
-      const int ldi = (int)P.ldi;
-      int p = ptr[u];
-      for (;;) {
-        const int qs = (p & ~7) + lane * 8;
-        const uint4 sv = *(const uint4*)(row + min(qs, ldi - 8));
-        const uint32_t wd[4] = {sv.x, sv.y, sv.z, sv.w};
-        int fp = 0x7fffffff;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int id = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-          const int q = qs + j;
-          const bool ok = q >= p && q < s_m && !is_ins(bits, id < n ? id : 0);
-          fp = ok ? min(fp, q) : fp;
-        }
-        const int f = wave_min_i32(fp);
-        if (f != 0x7fffffff) {
-          p = f;
-          break;
-        }
-        p = (p & ~7) + kWave * 8;
-        if (p >= s_m) {
-          p = s_m;
-          break;
-        }
-      }
-      if (lane == 0 && p > (int)ptr[u]) ptr[u] = (uint16_t)p;
-    }
     __syncthreads();
     TMFG_LAP(6);
     const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
@@ -802,6 +799,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     if (tid == 0) {
       s_nsweep = 0;
       s_next = 0;
+      s_adv = 0;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -907,6 +905,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           s_nnew = 3;
           sel[0] = f1 >> 6;
           sel[1] = F >> 6;       // F is even, so F and F + 1 share a chunk
+          // u's bit and the four rows are written: the advancing waves may start
+          __hip_atomic_store(&s_adv, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
         // The chunks of the three new faces are reloaded. Faces whose cached vertex was u
         // are stale now; the chunks whose maximum is stale and ranks above the best fresh
@@ -946,6 +946,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           s_nwork = 0;
           s_nnew = 0;
           s_nsel = 0;
+          __hip_atomic_store(&s_adv, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       } else {
         // Stale maximum: load every chunk whose maximum is stale and ranks above the best
@@ -957,6 +958,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         const int ns = Paper ? pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, sl_lane, &rest)
                              : append_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, sl_lane);
         if (lane == 0) {
+          __hip_atomic_store(&s_adv, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           s_nsel = ns;
           s_floor = kf;
           s_nwork = 0;
@@ -973,6 +975,20 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           }
         }
       }
+    } else if (wave >= kWaves - 4) {
+      // The new faces share the new vertex u, whose row no walk has read (a vertex is a face
+      // corner only once inserted): its position is 0 while its most similar vertices (its
+      // cluster) are mostly inserted already. The new faces' walks, usually the deepest of the
+      // next phase, would each cross that stretch. Once the selection above has named u and
+      // the corners of the face it split (a bounded wait; past the bound nothing is done,
+      // which changes no result), the last four waves move those four rows' positions to
+      // their first uninserted entries, beside the rest of the selection.
+      int st = 0;
+      for (int it = 0; it < 8192 && st == 0; ++it) {
+        st = __hip_atomic_load(&s_adv, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (st == 0) __builtin_amdgcn_s_sleep(1);
+      }
+      if (st == 1) advance_row(P.idx, (int)P.ldi, bits, ptr, s_u4[kWaves - 1 - wave], s_m, n, lane);
     }
     __syncthreads();
     TMFG_LAP(5);
