@@ -302,7 +302,8 @@ tmfg_status tmfg_seed(tmfg_plan plan, const float* W, int32_t n, double* scores,
    orig-tmfg): for face f with corners faces[3f..3f+2] (any order), best_u[f] = the
    vertex u with bit u clear in `inserted` (ceil(n/32) words, bit u of word u/32)
    maximising the float32 gain, lowest u on ties, and best_gain[f] its gain; -1 and
-   -inf when every vertex is marked. Reads three full rows of W per face. */
+   -inf when every vertex is marked; -2 and NaN for a face with a corner outside [0, n),
+   whose rows are not read. Reads three full rows of W per face. */
 tmfg_status tmfg_face_sweep(tmfg_plan plan, const float* W, int32_t n, const int32_t* faces,
                             int32_t nfaces, const uint32_t* inserted, int32_t* best_u,
                             float* best_gain, hipStream_t stream);

@@ -156,6 +156,20 @@ def _need(t, dtype, name: str):
     return t
 
 
+def _shape(t, name: str, ndim: int, cols: Optional[int] = None, square: bool = False):
+    """Host-side shape check, made before anything reaches the device: the kernels read
+    exactly the extents the header states, so a tensor of another shape is refused here."""
+    if t is None:
+        return
+    shape = tuple(t.shape)
+    if len(shape) != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions, got shape {shape}")
+    if square and shape[0] != shape[1]:
+        raise ValueError(f"{name} must be square, got shape {shape}")
+    if cols is not None and shape[1] != cols:
+        raise ValueError(f"{name} must have {cols} columns, got shape {shape}")
+
+
 def footprint_bytes(n_max: int, L_max: int, flags: int = 0) -> int:
     return int(_lib().tmfg_footprint_bytes(n_max, L_max, flags))
 
@@ -254,11 +268,15 @@ def build(X=None, W=None, plan: Optional[Plan] = None, stream=None, keep_w: bool
     import torch
     if (X is None) == (W is None):
         raise ValueError("give exactly one of X and W")
+    _shape(X, "X", 2)
+    _shape(W, "W", 2, square=True)
     src = _need(X if X is not None else W, torch.float32, "X" if X is not None else "W")
     n = src.shape[0]
     L = src.shape[1] if X is not None else 0
     if plan is None:
         plan = Plan(n, max(L, 2), flags)
+    if out is not None and (out.order.numel() != n or (keep_w and out.W is None)):
+        raise ValueError(f"out was allocated for n = {out.order.numel()}, not {n}")
     res = out if out is not None else alloc_result(n, src.device, keep_w)
     job = make_job(n, L, X, W, res)
     _check(_lib().tmfg_build(plan.handle, ctypes.byref(job), _stream(stream)), "tmfg_build")
@@ -269,6 +287,7 @@ def build(X=None, W=None, plan: Optional[Plan] = None, stream=None, keep_w: bool
 def correlation(X, plan: Optional[Plan] = None, stream=None):
     """Pearson similarity (float32, MFMA). Returns (W, status tensor)."""
     import torch
+    _shape(X, "X", 2)
     X = _need(X, torch.float32, "X")
     n, L = X.shape
     if plan is None:
@@ -288,6 +307,7 @@ def sort_rows(W, plan: Optional[Plan] = None, stream=None, with_values: bool = F
     """Per-vertex order as an (n, ld) int16 tensor holding uint16 ids (first n-1 valid),
     plus the (n, ld) float32 similarities in that order when with_values is set."""
     import torch
+    _shape(W, "W", 2, square=True)
     W = _need(W, torch.float32, "W")
     n = W.shape[0]
     if plan is None:
@@ -303,6 +323,7 @@ def sort_rows(W, plan: Optional[Plan] = None, stream=None, with_values: bool = F
 def seed(W, plan: Optional[Plan] = None, stream=None):
     """Seed scores (float64) and the four seed vertices."""
     import torch
+    _shape(W, "W", 2, square=True)
     W = _need(W, torch.float32, "W")
     n = W.shape[0]
     if plan is None:
@@ -316,10 +337,14 @@ def seed(W, plan: Optional[Plan] = None, stream=None):
 def face_sweep(W, faces, inserted_words, plan: Optional[Plan] = None, stream=None):
     """Exact best vertex per face by a full sweep. faces: (F, 3) int32; inserted: int32 words."""
     import torch
+    _shape(W, "W", 2, square=True)
+    _shape(faces, "faces", 2, cols=3)
+    n = W.shape[0]
+    if inserted_words is None or inserted_words.dim() != 1 or inserted_words.numel() < (n + 31) // 32:
+        raise ValueError(f"inserted must be a 1-D tensor of at least {(n + 31) // 32} words")
     W = _need(W, torch.float32, "W")
     faces = _need(faces, torch.int32, "faces")
     inserted_words = _need(inserted_words, torch.int32, "inserted")
-    n = W.shape[0]
     if plan is None:
         plan = Plan(n, 2)
     F = faces.shape[0]
@@ -344,6 +369,9 @@ class Batch:
         self.results = []
         jobs = (Job * len(self.inputs))()
         for i, (kind, t) in enumerate(self.inputs):
+            if kind not in ("X", "W"):
+                raise ValueError(f"input {i}: kind must be 'X' or 'W', got {kind!r}")
+            _shape(t, f"input {i} ({kind})", 2, square=kind == "W")
             t = _need(t, torch.float32, kind)
             n = t.shape[0]
             res = alloc_result(n, t.device, keep_w)
@@ -403,6 +431,7 @@ class Server:
         """Queue a build of the (n, L) float32 series X (host memory, copied at once)."""
         import numpy as np
         X = np.ascontiguousarray(X, dtype=np.float32)
+        _shape(X, "X", 2)
         n, L = X.shape
         t = ctypes.c_int64()
         _check(_lib().tmfg_server_submit(self._h, X.ctypes.data, n, L, int(arrival_ns), ctypes.byref(t)),
@@ -455,9 +484,14 @@ def dbht(W, order, edges, steps, k: int, n_threads: int = 0) -> dict:
         return np.ascontiguousarray(np.asarray(a), dtype=dtype)
 
     Wh = host(W, np.float32)
+    _shape(Wh, "W", 2, square=True)
     n = Wh.shape[0]
-    order_h, edges_h = host(order, np.int32), host(edges, np.int32).reshape(-1, 2)
+    order_h, edges_h = host(order, np.int32).ravel(), host(edges, np.int32).reshape(-1, 2)
     steps_h = host(steps, np.int32).reshape(-1, 4) if n > 4 else np.zeros((0, 4), np.int32)
+    # the C call reads exactly these extents
+    for name, a, rows in (("order", order_h, n), ("edges", edges_h, 3 * n - 6), ("steps", steps_h, max(n - 4, 0))):
+        if a.shape[0] != rows:
+            raise ValueError(f"{name} must have {rows} rows for n = {n}, got {a.shape[0]}")
     labels = np.empty(n, np.int32)
     linkage = np.empty((max(n - 1, 0), 4), np.float64)
     group = np.empty(n, np.int32)

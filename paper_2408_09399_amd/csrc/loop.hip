@@ -320,7 +320,8 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
 
 // ---------------------------------------------------------------------------------------
 // Bulk exact best vertex of many faces by sweeping their three rows (one workgroup per
-// face). Reads 12n bytes of W plus the n-bit inserted set per face.
+// face). Reads 12n bytes of W plus the n-bit inserted set per face. A face with a corner
+// outside [0, n) reads nothing and gets best_u = -2 and a NaN gain.
 // ---------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void face_sweep_kernel(const float* __restrict__ W, int n,
                                                          const int32_t* __restrict__ faces, int nfaces,
@@ -331,6 +332,13 @@ __global__ __launch_bounds__(256) void face_sweep_kernel(const float* __restrict
   const int f = blockIdx.x;
   if (f >= nfaces) return;
   int a = faces[3 * f], b = faces[3 * f + 1], c = faces[3 * f + 2];
+  if ((unsigned)a >= (unsigned)n || (unsigned)b >= (unsigned)n || (unsigned)c >= (unsigned)n) {
+    if (threadIdx.x == 0) {      // the whole workgroup leaves here: no barrier is skipped by part of it
+      best_u[f] = -2;
+      best_gain[f] = __builtin_nanf("");
+    }
+    return;
+  }
   sort3(a, b, c);
   const float* Wa = W + (size_t)a * n;
   const float* Wb = W + (size_t)b * n;

@@ -100,3 +100,41 @@ def test_server_host_side_argument_errors():
     a = lib.tmfg_server_now_ns()
     b = lib.tmfg_server_now_ns()
     assert 0 < a <= b
+
+
+def test_binding_refuses_wrong_shapes_before_the_device():
+    """The Python layer checks every extent the C calls read, before any device work: the
+    tensors here are host tensors, so a check made after the device check would fail with
+    another message."""
+    import numpy as np
+    import torch
+    import paper_2408_09399_amd as tm
+    with pytest.raises(ValueError, match="square"):
+        tm.build(W=torch.zeros(6, 7))
+    with pytest.raises(ValueError, match="2 dimensions"):
+        tm.build(X=torch.zeros(24))
+    with pytest.raises(ValueError, match="square"):
+        tm.sort_rows(torch.zeros(6, 5))
+    with pytest.raises(ValueError, match="square"):
+        tm.seed(torch.zeros(5, 6))
+    with pytest.raises(ValueError, match="3 columns"):
+        tm.face_sweep(torch.zeros(40, 40), torch.zeros(5, 2, dtype=torch.int32), torch.zeros(2, dtype=torch.int32))
+    with pytest.raises(ValueError, match="at least 2 words"):
+        tm.face_sweep(torch.zeros(40, 40), torch.zeros(5, 3, dtype=torch.int32), torch.zeros(1, dtype=torch.int32))
+    with pytest.raises(ValueError, match="kind"):
+        tm.Batch([("Y", torch.zeros(8, 8))])
+    with pytest.raises(ValueError, match="square"):
+        tm.Batch([("W", torch.zeros(8, 9))])
+    n = 8
+    W = np.eye(n, dtype=np.float32)
+    order = np.arange(n, dtype=np.int32)
+    edges = np.zeros((3 * n - 6, 2), np.int32)
+    steps = np.zeros((n - 4, 4), np.int32)
+    with pytest.raises(ValueError, match="order must have 8 rows"):
+        tm.dbht(W, order[:-1], edges, steps, 2)
+    with pytest.raises(ValueError, match="edges must have 18 rows"):
+        tm.dbht(W, order, edges[:-1], steps, 2)
+    with pytest.raises(ValueError, match="steps must have 4 rows"):
+        tm.dbht(W, order, edges, steps[:-1], 2)
+    with pytest.raises(ValueError, match="square"):
+        tm.dbht(W[:, :-1], order, edges, steps, 2)

@@ -101,3 +101,22 @@ def test_face_sweep(n, levels):
         u, g = oracle.face_best(W, sorted(faces[f].tolist()), ins)
         assert bu[f] == u, f
         assert np.float32(bg[f]).tobytes() == np.float32(g).tobytes(), f
+
+
+def test_face_sweep_corner_out_of_range():
+    """A face with a corner outside [0, n) reads no row: best_u -2, NaN gain; the faces
+    around it are swept as usual."""
+    n = 300
+    W = synth.random_symmetric(n, 5)
+    faces = np.array([[0, 1, 2], [-1, 4, 5], [7, n, 9], [10, 11, 1 << 30], [20, 30, 40]], np.int32)
+    ins = np.zeros(n, dtype=bool)
+    words = np.zeros((n + 31) // 32, dtype=np.uint32)
+    bu, bg = tm.face_sweep(to_dev(W), to_dev(faces), to_dev(words.view(np.int32)))
+    torch.cuda.synchronize()
+    bu, bg = bu.cpu().numpy(), bg.cpu().numpy()
+    assert bu[1:4].tolist() == [-2, -2, -2] and np.isnan(bg[1:4]).all()
+    for f in (0, 4):          # nothing is marked inserted, so every vertex competes
+        u, g = oracle.face_best(W, sorted(faces[f].tolist()), ins)
+        assert bu[f] == u, f
+        assert np.float32(bg[f]).tobytes() == np.float32(g).tobytes(), f
+
