@@ -100,7 +100,8 @@ typedef struct {
   int32_t L;            /* series length; ignored when X is NULL */
   const float* X;       /* n x L series, or NULL */
   const float* W;       /* n x n similarity, finite and bitwise symmetric, or NULL */
-  float* W_out;         /* optional n x n: the float32 similarity the build used */
+  float* W_out;         /* optional n x n: the float32 similarity the build used (may be W
+                           itself, which is then left as it is) */
   int32_t* order;       /* n: v1..v4 (seed rank order), then vertices in insertion order */
   int32_t* edges;       /* (3n-6) x 2: (v1,v2),(v1,v3),(v1,v4),(v2,v3),(v2,v4),(v3,v4),
                            then (u,x),(u,y),(u,z) for each step */

@@ -425,7 +425,7 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
   for (int i = 0; i < count; ++i) {
     tmfg::batch_job_desc(jobs[i], cur, hj[i]);
     cur += b->spec.scratch[i];
-    if (jobs[i].W && jobs[i].W_out) {
+    if (jobs[i].W && jobs[i].W_out && jobs[i].W_out != jobs[i].W) {
       L.w_copies.push_back({jobs[i].W, jobs[i].W_out});
       L.w_copy_bytes.push_back((size_t)jobs[i].n * jobs[i].n * 4);
     }

@@ -228,7 +228,7 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
     Wt = Wdst;
   } else {
     if (!(plan->flags & TMFG_NO_VALIDATE)) TMFG_HIP(tmfg::launch_validate(job->W, n, plan->dflags, stream));
-    if (job->W_out)
+    if (job->W_out && job->W_out != job->W)
       TMFG_HIP(hipMemcpyAsync(job->W_out, job->W, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, stream));
     Wt = job->W;
   }

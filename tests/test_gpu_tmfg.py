@@ -109,6 +109,35 @@ def test_repeat_determinism():
         assert blob == first
 
 
+@pytest.mark.parametrize("batched", [False, True])
+def test_w_out_same_as_w(batched):
+    """W_out may be the caller's W itself (a single build, and a batch through the C ABI):
+    the build leaves W as it is and gives the oracle's result."""
+    import ctypes
+    from paper_2408_09399_amd import binding
+    n = 300
+    W = synth.random_symmetric(n, 41)
+    Wd = to_dev(W)
+    res = tm.alloc_result(n, Wd.device)
+    res.W = Wd
+    if batched:
+        lib = binding.lib()
+        jobs = (binding.Job * 1)()
+        jobs[0] = binding.make_job(n, 0, None, Wd, res)
+        h = ctypes.c_void_p()
+        assert lib.tmfg_batch_create(ctypes.byref(h), ctypes.cast(jobs, ctypes.c_void_p), 1, 0) == 0
+        assert lib.tmfg_batch_run(h, None) == 0
+        torch.cuda.synchronize()
+        assert lib.tmfg_batch_destroy(h) == 0
+    else:
+        tm.build(W=Wd, out=res)
+        torch.cuda.synchronize()
+    got = res.to_numpy()
+    assert got["status"] == 0
+    assert got["W"].tobytes() == W.tobytes()
+    same_tmfg(got, oracle.tmfg_lazy(W))
+
+
 def test_device_errors():
     W = synth.random_symmetric(50, 1)
     W2 = W.copy()
