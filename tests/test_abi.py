@@ -138,3 +138,15 @@ def test_binding_refuses_wrong_shapes_before_the_device():
         tm.dbht(W, order, edges, steps[:-1], 2)
     with pytest.raises(ValueError, match="square"):
         tm.dbht(W[:, :-1], order, edges, steps, 2)
+
+
+def test_missing_library_raises(monkeypatch):
+    """Without libtmfg.so the binding raises at the first call: there is no CPU fallback."""
+    import torch
+    import paper_2408_09399_amd as tm
+    monkeypatch.setattr(binding, "_LIB", None)
+    monkeypatch.setattr(binding, "LIB_PATH", os.path.join(ROOT, "no_such_dir", "libtmfg.so"))
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        binding.lib()
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        tm.footprint_bytes(100, 16)
