@@ -143,9 +143,9 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    deepest walk's rounds, [13] walks of 4 or more rounds, [14] walks of 16 or more rounds,
    [15] skip scans over fully inserted stretches, [16..19] microseconds one walk group
    spent loading and ranking list entries, reading candidate similarities, updating
-   bounds, and skip-scanning (diagnostics: 0 unless the library is built with the walk timers
-   on, kWalkDiag in loop.hip, which waits for every load and so slows the walks), [20] selection phases that found a stale
-   maximum, [21] phases with more stale faces than one phase recomputes, [22] phases that
+   bounds, and skip-scanning (diagnostics: 0 unless the library is built with the walk
+   timers on, kWalkDiag in loop.hip, which wait for every load and so slow the walks),
+   [20] selection phases that found a stale maximum, [21] phases with more stale faces than one phase recomputes, [22] phases that
    loaded the most chunks one phase loads, [23] recomputed pairs that were not committed
    because a pair taken before them in heap order might change them (TMFG_RULE_PAPER),
    [24] row compactions, [25..31] reserved (0). From n = 512 on, a single build runs its
