@@ -145,17 +145,17 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    spent loading and ranking list entries, reading candidate similarities, updating
    bounds, and skip-scanning (diagnostics: 0 unless the library is built with the walk
    timers on, kWalkDiag in loop.hip, which wait for every load and so slow the walks),
-   [20] selection phases that found a stale maximum, [21] phases with more stale faces than one phase recomputes, [22] phases that
-   loaded the most chunks one phase loads, [23] recomputed pairs that were not committed
-   because a pair taken before them in heap order might change them (TMFG_RULE_PAPER),
-   [24] row compactions, [25..31] reserved (0). From n = 512 on, a single build runs its
-   loop in segments (every rule): it stops after n - n/4, n - n/8, ... insertions (under
-   TMFG_RULE_CORR at the first round boundary at or past each count), as long as at least
-   128 vertices are left, and every sorted row drops its inserted entries (in place, order
-   kept) before the loop resumes; results do not depend on it. Under
-   TMFG_RULE_PAPER, [1] counts scans for the first uninserted
-   entry of the corners' sorted rows instead of walk rounds. Under TMFG_RULE_CORR only these
-   are kept: [0] faces recomputed because their pair vertex was inserted, [1] row scans,
+   [20] selection phases that found a stale maximum, [21] phases with more stale faces
+   than one phase recomputes, [22] phases that loaded the most chunks one phase loads,
+   [23] recomputed pairs that were not committed because a pair taken before them in heap
+   order might change them (TMFG_RULE_PAPER), [24] row compactions, [25..31] reserved (0).
+   From n = 512 on, a single build runs its loop in segments (every rule): it stops after
+   n - n/4, n - n/8, ... insertions (under TMFG_RULE_CORR at the first round boundary at or
+   past each count), as long as at least 128 vertices are left, and every sorted row drops
+   its inserted entries (in place, order kept) before the loop resumes; results do not
+   depend on it. Under TMFG_RULE_PAPER, [1] counts scans for the first uninserted entry of
+   the corners' sorted rows instead of walk rounds. Under TMFG_RULE_CORR only these are
+   kept: [0] faces recomputed because their pair vertex was inserted, [1] row scans,
    [2] extra passes (a round with more faces to recompute than one pass takes), [3] rounds,
    [5..9] microseconds in the scan for faces to recompute, their pairs, publishing,
    rebuilding chunk maxima and selection, [10] microseconds of the kernel, [24] row
