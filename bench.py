@@ -508,7 +508,7 @@ def bench_dbht(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; use --gpus 1"}))
+        print(json.dumps({"error": "the library builds on one GPU per process (no multi-GPU path); use --gpus 1"}))
         sys.exit(2)
     if args.calibration_copy:
         calibration_copy()
@@ -541,7 +541,7 @@ def main():
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
-        phases.append(plan.phase_ms())      # waits for this build's last event
+        phases.append(plan.phase_ms())      # waits for the last event of the TMFG build above
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     status = int(res.status.item())

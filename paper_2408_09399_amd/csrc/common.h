@@ -7,7 +7,7 @@ namespace tmfg {
 
 constexpr int kWave = 64;
 
-// Limits of this build. Rows are sorted inside one workgroup's LDS (6 bytes per element
+// Limits of the library. Rows are sorted inside one workgroup's LDS (6 bytes per element
 // plus the bucket table), which caps n; vertex and face ids are packed as 16 bits.
 constexpr int kMaxN = 20480;
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 workgroup
