@@ -46,7 +46,7 @@ invariants.py.
 from __future__ import annotations
 
 import heapq
-from typing import Dict, List, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -178,8 +178,11 @@ def tmfg_exact(W: np.ndarray) -> Dict[str, np.ndarray]:
     return _result(order, edges, steps, gains, faces)
 
 
-def tmfg_lazy(W: np.ndarray) -> Dict[str, np.ndarray]:
-    """Lazy heap schedule (Section 4.2): a stale pair is recomputed only when popped."""
+def tmfg_lazy(W: np.ndarray, max_steps: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Lazy heap schedule (Section 4.2): a stale pair is recomputed only when popped.
+
+    max_steps stops the schedule after that many insertions (to time a prefix of it); the
+    result then holds the steps taken and the faces at that point."""
     W = _check(W)
     n = W.shape[0]
     seed = seed_vertices(W)
@@ -194,7 +197,7 @@ def tmfg_lazy(W: np.ndarray) -> Dict[str, np.ndarray]:
             heap.append((-float(g), f, u))
         heapq.heapify(heap)
     steps, gains = [], []
-    while len(order) < n:
+    while len(order) < n and (max_steps is None or len(steps) < max_steps):
         neg_g, f, u = heapq.heappop(heap)       # largest gain, then lowest face id
         if inserted[u]:
             u2, g2 = face_best(W, faces[f], inserted)

@@ -101,3 +101,18 @@ def test_signed_zero_gain_recorded_positive():
         r = fn(W)
         assert r["step_gain"].view(np.uint32).tolist() == [0]
         oracle.check_tmfg(W, r)
+
+
+def test_lazy_prefix_is_the_full_schedules_prefix():
+    """tmfg_lazy(W, max_steps=k) stops after k insertions of the same schedule (the CPU
+    baseline times such a prefix): its order, steps and gains are the full run's first k."""
+    from paper_2408_09399_amd import synth
+    W = synth.random_symmetric(120, 9)
+    full = oracle.tmfg_lazy(W)
+    for k in (0, 1, 37, 116):
+        r = oracle.tmfg_lazy(W, max_steps=k)
+        assert np.array_equal(r["order"], full["order"][:4 + k])
+        assert np.array_equal(r["steps"], full["steps"][:k])
+        assert r["step_gain"].tobytes() == full["step_gain"][:k].tobytes()
+        assert r["faces"].shape == (4 + 2 * k, 3)
+    assert all(np.array_equal(oracle.tmfg_lazy(W, max_steps=116)[key], full[key]) for key in full)
