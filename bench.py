@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--no-serial", action="store_true", help="c5: skip the serial plain-build comparison")
     ap.add_argument("--fifo", action="store_true", help="c5: dispatch strictly in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=1500)
+    ap.add_argument("--cpu-sample-steps", type=int, default=8000)
     ap.add_argument("--rule", default="exact", choices=["exact", "paper", "corr"],
                     help="face rule: exact greedy, the paper's heap rule (Algorithm 2), or corr-tmfg "
                          "with a prefix size (Algorithm 1)")
