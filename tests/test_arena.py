@@ -17,7 +17,10 @@ def harness(tmp_path_factory):
     if shutil.which("g++") is None:
         pytest.skip("g++ not available")
     exe = str(tmp_path_factory.mktemp("arena") / "arena_check")
-    subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, os.path.join(ROOT, "tests", "arena_check.cpp"),
+    # host-only harness, built with AddressSanitizer and UndefinedBehaviorSanitizer: a bad
+    # access or undefined behaviour in the allocator ends it with a non-zero status
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                    "-fno-sanitize-recover=undefined", "-I", CSRC, os.path.join(ROOT, "tests", "arena_check.cpp"),
                     "-o", exe], check=True)
     return exe
 
