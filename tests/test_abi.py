@@ -150,3 +150,42 @@ def test_missing_library_raises(monkeypatch):
         binding.lib()
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         tm.footprint_bytes(100, 16)
+
+
+def test_batch_footprint_host_side():
+    """tmfg_batch_footprint_bytes checks every job and sizes its scratch on the host (no
+    device call): the pointers below are placeholders it only tests for NULL."""
+    lib = binding.lib()
+    P = 0x1000
+
+    def job(n, L=0, X=False, W_out=False, steps=True):
+        j = binding.Job()
+        j.n, j.L = n, L
+        j.X, j.W = (P, None) if X else (None, P)
+        j.W_out = P if W_out else None
+        j.order = j.edges = j.faces = j.status = P
+        j.steps = j.step_gain = P if steps else None
+        return j
+
+    def fp(*jobs):
+        arr = (binding.Job * len(jobs))(*jobs)
+        return lib.tmfg_batch_footprint_bytes(ctypes.cast(arr, ctypes.c_void_p), len(jobs), 0)
+
+    assert fp(job(3)) == 0 and fp(job(20481)) == 0          # n outside [4, 20480]
+    assert fp(job(100, steps=False)) == 0                   # steps needed from n = 5
+    assert fp(job(4, steps=False)) > 0
+    neither = job(100)
+    neither.W = None
+    assert fp(neither) == 0                                 # exactly one of X and W
+    assert fp(job(100, L=1, X=True)) == 0                   # L < 2
+    assert fp(job(100), neither) == 0                       # one bad job spoils the batch
+    n, L = 1000, 256
+    ldi = (n - 1 + 7) // 8 * 8
+    w = fp(job(n))
+    x = fp(job(n, L, X=True))
+    xo = fp(job(n, L, X=True, W_out=True))
+    assert w >= 6 * n * ldi                                 # sorted ids and values
+    assert x - xo >= 4 * n * n                              # its own W without a W_out
+    assert xo - w >= n * L * 4                              # the standardised series
+    two = fp(job(n), job(500))
+    assert two - w >= 6 * 500 * ((499 + 7) // 8 * 8)
