@@ -350,6 +350,19 @@ tmfg_status tmfg_dbht(int32_t n, const float* W, const int32_t* order, const int
 const char* tmfg_status_string(tmfg_status s);
 int tmfg_last_hip_error(void);
 
+/* Latency of one dependent trip to memory from one wave, in nanoseconds: the floor of a
+   chain of loads each of whose addresses is the value of the one before, as in the
+   insertion loop (a list entry names the similarity read next). The call allocates a
+   buffer of about `bytes` bytes (rounded down to a power of two of 128-byte lines, at
+   least 64 lines, at most 16 GiB), links its lines into one cycle in a scattered order,
+   and times `steps` (1..2^24) trips of one wave: with lanes == 1 every lane reads the same
+   line (one line per trip), with lanes == 64 each lane follows its own stretch of the
+   cycle (64 lines per trip, a gather). A buffer of at most 2 MiB (half of one L2) is read
+   once untimed by the same wave, so the timed pass gives the L2 latency; a larger one is
+   timed cold, and one of several GiB, of which each line is read at most once, gives the
+   HBM latency. Synchronous, on the current device; frees what it allocates. */
+tmfg_status tmfg_probe_load_latency(int64_t bytes, int32_t lanes, int32_t steps, double* ns_per_trip);
+
 #ifdef __cplusplus
 }
 #endif

@@ -67,6 +67,7 @@ SIGNATURES = {
     "tmfg_dbht": (_I, [_I, _P, _P, _P, _P, _I, _I, _P, _P, _P, _P]),
     "tmfg_status_string": (ctypes.c_char_p, [_I]),
     "tmfg_last_hip_error": (ctypes.c_int, []),
+    "tmfg_probe_load_latency": (_I, [ctypes.c_int64, _I, _I, ctypes.POINTER(ctypes.c_double)]),
 }
 
 
@@ -500,3 +501,11 @@ def dbht(W, order, edges, steps, k: int, n_threads: int = 0) -> dict:
     _check(_lib().tmfg_dbht(n, p(Wh), p(order_h), p(edges_h), p(steps_h), int(k), int(n_threads), p(labels),
                             p(linkage), p(group), p(bubble)), "tmfg_dbht")
     return {"labels": labels, "linkage": linkage, "group": group, "bubble": bubble}
+
+
+def load_latency_ns(bytes_: int, lanes: int = 64, steps: int = 20000) -> float:
+    """Nanoseconds per dependent trip to memory from one wave (tmfg_probe_load_latency)."""
+    out = ctypes.c_double()
+    _check(_lib().tmfg_probe_load_latency(int(bytes_), int(lanes), int(steps), ctypes.byref(out)),
+           "tmfg_probe_load_latency")
+    return float(out.value)

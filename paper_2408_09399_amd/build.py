@@ -25,7 +25,7 @@ FLAGS = [
     "-Wall", "-Wno-unused-function",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
-SOURCES = ["pearson.hip", "seed.hip", "sort.hip", "loop.hip", "corr.hip", "batch.hip", "server.hip", "capi.hip",
+SOURCES = ["pearson.hip", "seed.hip", "sort.hip", "loop.hip", "corr.hip", "batch.hip", "server.hip", "capi.hip", "probe.hip",
            "dbht.cpp"]
 
 

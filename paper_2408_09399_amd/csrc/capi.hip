@@ -64,22 +64,52 @@ Sizes sizes_for(int n, int L) {
   return s;
 }
 
+// The device scratch of one build: where each buffer sits in one region of `bytes`
+// bytes, every buffer on a 256-byte boundary.
+struct Scratch {
+  float* Z;
+  float* W;
+  uint16_t* idx;
+  float* vals;
+  double* scores;
+  uint4* frec;
+  uint32_t* dflags;
+  int32_t* stats;
+  uint8_t* lstate;
+  size_t bytes;
+};
+
+Scratch carve(uint8_t* base, int n, int L) {
+  const Sizes s = sizes_for(n, L);
+  Scratch r{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    uint8_t* p = base ? base + off : nullptr;
+    off += (size_t)tmfg::round_up((int64_t)(bytes < 256 ? 256 : bytes), 256);
+    return p;
+  };
+  r.Z = (float*)take(s.z_bytes);
+  r.W = (float*)take(s.w_bytes);
+  r.idx = (uint16_t*)take(s.idx_bytes);
+  r.vals = (float*)take(s.vals_bytes);
+  r.scores = (double*)take(s.scores_bytes);
+  r.frec = (uint4*)take(s.frec_bytes);
+  r.dflags = (uint32_t*)take(4);
+  r.stats = (int32_t*)take(128);
+  r.lstate = take(tmfg::loop_state_bytes(n));
+  r.bytes = off;
+  return r;
+}
+
 }  // namespace
 
 struct tmfg_plan_s {
   int device = 0;
   int n_max = 0, L_max = 0;
   uint32_t flags = 0;
-  Sizes sz{};
-  float* Z = nullptr;
-  float* W = nullptr;
-  uint16_t* idx = nullptr;
-  float* vals = nullptr;
-  double* scores = nullptr;
-  uint4* frec = nullptr;
-  uint32_t* dflags = nullptr;
-  int32_t* stats = nullptr;
-  uint8_t* lstate = nullptr;   // the insertion loop's state between segments
+  uint8_t* region = nullptr;    // one allocation holding the scratch below
+  Scratch sc{};                 // similarity, standardised series, sorted rows, face records,
+                                // flags, counters, the insertion loop's state between segments
   hipEvent_t ev[kPhaseEvents] = {};
   bool timed = false;
   tmfg_batch batch = nullptr;   // the last batch built through tmfg_build_batch
@@ -90,15 +120,7 @@ namespace {
 
 void plan_free(tmfg_plan p) {
   if (!p) return;
-  hipFree(p->Z);
-  hipFree(p->W);
-  hipFree(p->idx);
-  hipFree(p->vals);
-  hipFree(p->scores);
-  hipFree(p->frec);
-  hipFree(p->dflags);
-  hipFree(p->stats);
-  hipFree(p->lstate);
+  hipFree(p->region);
   for (auto& e : p->ev)
     if (e) hipEventDestroy(e);
   if (p->batch) tmfg_batch_destroy(p->batch);
@@ -118,7 +140,72 @@ tmfg_status alloc(void** ptr, size_t bytes) {
 bool valid_n(int n, int n_max) { return n >= tmfg::kMinN && n <= n_max && n <= tmfg::kMaxN; }
 
 void record(tmfg_plan p, int i, hipStream_t s) {
-  if (p->flags & TMFG_TIMING) hipEventRecord(p->ev[i], s);
+  if (p && (p->flags & TMFG_TIMING)) hipEventRecord(p->ev[i], s);
+}
+
+// Argument checks of a build job against the limits n_max and L_max (no GPU work).
+tmfg_status check_job(const tmfg_job* job, int n_max, int L_max) {
+  if (!job) return TMFG_E_INVALID;
+  const int n = job->n;
+  if ((job->X == nullptr) == (job->W == nullptr)) return TMFG_E_INVALID;
+  if (!job->order || !job->edges || !job->faces || !job->status) return TMFG_E_INVALID;
+  if (!valid_n(n, n_max)) return TMFG_E_SIZE;
+  if (n > 4 && (!job->steps || !job->step_gain)) return TMFG_E_INVALID;
+  if (job->X && (job->L < 2 || job->L > L_max)) return TMFG_E_SIZE;
+  return TMFG_OK;
+}
+
+// Enqueue one whole build on `stream` using the scratch `sc` (sized for at least this job).
+// `timed` (may be null) is the plan whose phase events are recorded.
+tmfg_status enqueue_build(const Scratch& sc, uint32_t flags, const tmfg_job* job, hipStream_t stream,
+                          tmfg_plan timed) {
+  const int n = job->n;
+  record(timed, 0, stream);
+  hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(1), 0, stream, sc.dflags);
+  TMFG_HIP(hipGetLastError());
+  const float* Wt;
+  if (job->X) {
+    const Sizes s = sizes_for(n, job->L);
+    float* Wdst = job->W_out ? job->W_out : sc.W;
+    TMFG_HIP(tmfg::launch_standardize(job->X, n, job->L, sc.Z, s.n_pad, s.L_pad, sc.dflags, stream));
+    TMFG_HIP(tmfg::launch_corr_gemm(sc.Z, n, s.L_pad, Wdst, stream));
+    Wt = Wdst;
+  } else {
+    if (!(flags & TMFG_NO_VALIDATE)) TMFG_HIP(tmfg::launch_validate(job->W, n, sc.dflags, stream));
+    if (job->W_out && job->W_out != job->W)
+      TMFG_HIP(hipMemcpyAsync(job->W_out, job->W, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    Wt = job->W;
+  }
+  record(timed, 1, stream);
+  TMFG_HIP(tmfg::launch_seed_scores(Wt, n, sc.scores, stream));
+  record(timed, 2, stream);
+  const int64_t ldi = tmfg::sort_row_stride(n);
+  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, sc.idx, sc.vals, ldi, stream));
+  record(timed, 3, stream);
+  tmfg::LoopParams P{};
+  P.W = Wt;
+  P.n = n;
+  P.idx = sc.idx;
+  P.vals = sc.vals;
+  P.ldi = ldi;
+  P.scores = sc.scores;
+  P.frec = sc.frec;
+  P.flags = sc.dflags;
+  P.order = job->order;
+  P.edges = job->edges;
+  P.steps = job->steps;
+  P.step_gain = job->step_gain;
+  P.faces = job->faces;
+  P.status = job->status;
+  P.stats = sc.stats;
+  P.m = n - 1;
+  P.stop_at = INT_MAX;
+  P.state = sc.lstate;
+  P.max_rounds = tmfg::kWalkRounds;
+  tmfg::rule_from_flags(flags, &P.paper, &P.prefix);
+  TMFG_HIP(tmfg::launch_loop_compacting(P, sc.idx, sc.vals, stream));
+  record(timed, 4, stream);
+  return TMFG_OK;
 }
 
 }  // namespace
@@ -146,9 +233,7 @@ int tmfg_last_hip_error(void) { return g_last_hip; }
 size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags) {
   (void)flags;
   if (n_max < tmfg::kMinN) return 0;
-  const Sizes s = sizes_for(n_max, L_max);
-  return s.z_bytes + s.w_bytes + s.idx_bytes + s.vals_bytes + s.scores_bytes + s.frec_bytes + 256 * 2 +
-         tmfg::loop_state_bytes(n_max);
+  return carve(nullptr, n_max, L_max < 2 ? 2 : L_max).bytes;
 }
 
 tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags) {
@@ -175,19 +260,13 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint
   p->n_max = n_max;
   p->L_max = L_max;
   p->flags = flags;
-  p->sz = sizes_for(n_max, L_max);
-  tmfg_status st;
-  if ((st = alloc((void**)&p->Z, p->sz.z_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->W, p->sz.w_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->idx, p->sz.idx_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->vals, p->sz.vals_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->scores, p->sz.scores_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->frec, p->sz.frec_bytes)) != TMFG_OK ||
-      (st = alloc((void**)&p->dflags, 4)) != TMFG_OK || (st = alloc((void**)&p->stats, 128)) != TMFG_OK ||
-      (st = alloc((void**)&p->lstate, tmfg::loop_state_bytes(n_max))) != TMFG_OK) {
+  const size_t bytes = carve(nullptr, n_max, L_max).bytes;
+  tmfg_status st = alloc((void**)&p->region, bytes);
+  if (st != TMFG_OK) {
     plan_free(p);
     return st;
   }
+  p->sc = carve(p->region, n_max, L_max);
   for (auto& ev : p->ev) {
     e = hipEventCreate(&ev);
     if (e != hipSuccess) {
@@ -208,59 +287,11 @@ tmfg_status tmfg_plan_destroy(tmfg_plan plan) {
 }
 
 tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) {
-  if (!plan || !job) return TMFG_E_INVALID;
-  const int n = job->n;
-  if ((job->X == nullptr) == (job->W == nullptr)) return TMFG_E_INVALID;
-  if (!job->order || !job->edges || !job->faces || !job->status) return TMFG_E_INVALID;
-  if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
-  if (n > 4 && (!job->steps || !job->step_gain)) return TMFG_E_INVALID;
-  if (job->X && (job->L < 2 || job->L > plan->L_max)) return TMFG_E_SIZE;
-
-  record(plan, 0, stream);
-  hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(1), 0, stream, plan->dflags);
-  TMFG_HIP(hipGetLastError());
-  const float* Wt;
-  if (job->X) {
-    const Sizes s = sizes_for(n, job->L);
-    float* Wdst = job->W_out ? job->W_out : plan->W;
-    TMFG_HIP(tmfg::launch_standardize(job->X, n, job->L, plan->Z, s.n_pad, s.L_pad, plan->dflags, stream));
-    TMFG_HIP(tmfg::launch_corr_gemm(plan->Z, n, s.L_pad, Wdst, stream));
-    Wt = Wdst;
-  } else {
-    if (!(plan->flags & TMFG_NO_VALIDATE)) TMFG_HIP(tmfg::launch_validate(job->W, n, plan->dflags, stream));
-    if (job->W_out && job->W_out != job->W)
-      TMFG_HIP(hipMemcpyAsync(job->W_out, job->W, (size_t)n * n * sizeof(float), hipMemcpyDeviceToDevice, stream));
-    Wt = job->W;
-  }
-  record(plan, 1, stream);
-  TMFG_HIP(tmfg::launch_seed_scores(Wt, n, plan->scores, stream));
-  record(plan, 2, stream);
-  const int64_t ldi = tmfg::sort_row_stride(n);
-  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, plan->idx, plan->vals, ldi, stream));
-  record(plan, 3, stream);
-  tmfg::LoopParams P{};
-  P.W = Wt;
-  P.n = n;
-  P.idx = plan->idx;
-  P.vals = plan->vals;
-  P.ldi = ldi;
-  P.scores = plan->scores;
-  P.frec = plan->frec;
-  P.flags = plan->dflags;
-  P.order = job->order;
-  P.edges = job->edges;
-  P.steps = job->steps;
-  P.step_gain = job->step_gain;
-  P.faces = job->faces;
-  P.status = job->status;
-  P.stats = plan->stats;
-  P.m = n - 1;
-  P.stop_at = INT_MAX;
-  P.state = plan->lstate;
-  P.max_rounds = tmfg::kWalkRounds;
-  tmfg::rule_from_flags(plan->flags, &P.paper, &P.prefix);
-  TMFG_HIP(tmfg::launch_loop_compacting(P, plan->idx, plan->vals, stream));
-  record(plan, 4, stream);
+  if (!plan) return TMFG_E_INVALID;
+  const tmfg_status st = check_job(job, plan->n_max, plan->L_max);
+  if (st != TMFG_OK) return st;
+  const tmfg_status e = enqueue_build(plan->sc, plan->flags, job, stream, plan);
+  if (e != TMFG_OK) return e;
   plan->timed = (plan->flags & TMFG_TIMING) != 0;
   return TMFG_OK;
 }
@@ -290,7 +321,7 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]) {
 
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]) {
   if (!plan || !out) return TMFG_E_INVALID;
-  TMFG_HIP(hipMemcpy(out, plan->stats, 128, hipMemcpyDeviceToHost));
+  TMFG_HIP(hipMemcpy(out, plan->sc.stats, 128, hipMemcpyDeviceToHost));
   for (int i = 5; i <= 10; ++i) out[i] = (int32_t)((int64_t)out[i] * 1000 / plan->wall_khz);
   for (int i = 16; i < 20; ++i) out[i] = (int32_t)((int64_t)out[i] * 1000 / plan->wall_khz);
   return TMFG_OK;
@@ -301,11 +332,11 @@ tmfg_status tmfg_correlation(tmfg_plan plan, const float* X, int32_t n, int32_t 
   if (!plan || !X || !W || !status) return TMFG_E_INVALID;
   if (!valid_n(n, plan->n_max) || L < 2 || L > plan->L_max) return TMFG_E_SIZE;
   const Sizes s = sizes_for(n, L);
-  hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(1), 0, stream, plan->dflags);
+  hipLaunchKernelGGL(reset_flags_kernel, dim3(1), dim3(1), 0, stream, plan->sc.dflags);
   TMFG_HIP(hipGetLastError());
-  TMFG_HIP(tmfg::launch_standardize(X, n, L, plan->Z, s.n_pad, s.L_pad, plan->dflags, stream));
-  TMFG_HIP(tmfg::launch_corr_gemm(plan->Z, n, s.L_pad, W, stream));
-  hipLaunchKernelGGL(flags_to_status_kernel, dim3(1), dim3(1), 0, stream, plan->dflags, status);
+  TMFG_HIP(tmfg::launch_standardize(X, n, L, plan->sc.Z, s.n_pad, s.L_pad, plan->sc.dflags, stream));
+  TMFG_HIP(tmfg::launch_corr_gemm(plan->sc.Z, n, s.L_pad, W, stream));
+  hipLaunchKernelGGL(flags_to_status_kernel, dim3(1), dim3(1), 0, stream, plan->sc.dflags, status);
   TMFG_HIP(hipGetLastError());
   return TMFG_OK;
 }
@@ -339,3 +370,4 @@ tmfg_status tmfg_face_sweep(tmfg_plan plan, const float* W, int32_t n, const int
 }
 
 }  // extern "C"
+

@@ -1,0 +1,109 @@
+"""The batched and served configurations at the sizes they are benchmarked at.
+
+* The whole 512-instance batch (n log-uniform over 64..4096, L uniform over 64..512),
+  replayed with autotuned launch configurations: every instance equals its own single build
+  bit for bit (W included), and the oracle on the largest instances.
+* Served requests of n log-uniform over 100..8000 with L = 256, some of them n >= 4096 (the
+  largest size class), arriving while earlier dispatches are still on the device: every
+  result equals its own single build, and the oracle on a sample that includes n >= 4096.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2408_09399_amd as tm
+from paper_2408_09399_amd import synth
+from gpu_util import to_dev, same_tmfg
+
+pytestmark = pytest.mark.gpu
+
+
+def _solo_builds(Xs, keep_w=True):
+    """One plain build per input on one plan, back to back (results kept on the device)."""
+    n_max = max(x.shape[0] for x in Xs)
+    L_max = max(x.shape[1] for x in Xs)
+    plan = tm.Plan(n_max, L_max)
+    outs = []
+    for x in Xs:
+        o = tm.alloc_result(x.shape[0], x.device, keep_w=keep_w)
+        tm.build(X=x, plan=plan, out=o)
+        outs.append(o)
+    torch.cuda.synchronize()
+    plan.close()
+    return outs
+
+
+def test_c4_full_batch_autotuned_equals_solo_and_oracle():
+    inst = synth.config_c4(512)
+    Xs = [to_dev(s.X) for s in inst]
+    print(f"c4: {len(inst)} instances, sum n = {sum(x.shape[0] for x in Xs)}", flush=True)
+    b = tm.Batch([("X", x) for x in Xs], keep_w=True, flags=tm.BATCH_AUTOTUNE)
+    cfg = b.config()
+    assert cfg["tune_trials"] > 0
+    solo = _solo_builds(Xs)
+    for rep in range(2):                              # two replays, as the benchmark repeats them
+        got = b.run()
+        torch.cuda.synchronize()
+        statuses = torch.cat([r.status for r in got]).cpu().numpy()
+        assert (statuses == 0).all(), np.flatnonzero(statuses)[:5]
+        for i, (g, s) in enumerate(zip(got, solo)):
+            assert torch.equal(g.W.view(torch.int32), s.W.view(torch.int32)), f"instance {i}: W differs"
+            for k in ("order", "edges", "steps", "faces"):
+                assert torch.equal(getattr(g, k), getattr(s, k)), f"instance {i} (n={g.order.numel()}): {k}"
+            assert torch.equal(g.step_gain.view(torch.int32), s.step_gain.view(torch.int32)), f"instance {i}: gains"
+    # the oracle, fed the same similarity bytes, on the two largest instances
+    sizes = np.array([x.shape[0] for x in Xs])
+    for i in np.argsort(-sizes, kind="stable")[:2]:
+        g = got[int(i)].to_numpy()
+        same_tmfg(g, oracle.tmfg_lazy(g["W"]))
+    b.close()
+
+
+def _c5_requests(count, seed):
+    """C5-shaped requests (n log-uniform over 100..8000, L = 256); three of them are forced
+    into the largest size class (n >= 4096), one at the top of the range."""
+    trace = synth.serving_trace(1.0, count, seed=seed)
+    Xs = [r.series.X for r in trace]
+    for slot, n in ((3, 8000), (9, 4096), (17, 5900)):
+        rng = np.random.default_rng(seed * 100 + slot)
+        k = int(rng.integers(2, 31))
+        Xs[slot] = synth.planted_clusters(n, 256, synth.dirichlet_sizes(rng, n, k), (0.3, 1.0),
+                                          seed=seed * 1000 + slot).X
+    return Xs
+
+
+def test_c5_sized_requests_arriving_in_flight_equal_solo_and_oracle():
+    Xs = _c5_requests(40, 17)
+    ns = [X.shape[0] for X in Xs]
+    assert max(ns) == 8000 and sum(n >= 4096 for n in ns) >= 3
+    srv = tm.Server(hbm_budget=32 << 30, host_budget=1 << 30, max_batch=16, n_streams=2, n_max=8192, L_max=256)
+    tickets = []
+    # the first eight at once; the rest one every 4 ms, so that most arrive while the
+    # dispatches of the earlier ones (the n = 8000 build among them) are on the device
+    for i, X in enumerate(Xs):
+        tickets.append(srv.submit(X))
+        if i >= 8:
+            time.sleep(0.004)
+    got = [srv.poll(t, wait_ms=-1) for t in tickets]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(Xs) and st["dispatches"] >= 3
+    # some request arrived after an earlier dispatch had started and was dispatched before
+    # that one finished
+    overlap = any(g1["dispatch_ns"] < g2["arrival_ns"] and g2["dispatch_ns"] < g1["done_ns"]
+                  for g1 in got for g2 in got)
+    assert overlap
+    solo = _solo_builds([to_dev(X) for X in Xs])
+    for i, (X, g, s) in enumerate(zip(Xs, got, solo)):
+        assert g["status"] == 0, (i, g["status"])
+        assert g["arrival_ns"] <= g["dispatch_ns"] <= g["done_ns"]
+        same_tmfg(g, s.to_numpy())
+    # the oracle on the smallest, a middle-sized and two of the largest-class requests
+    order = np.argsort(ns, kind="stable")
+    pick = {int(order[0]), int(order[len(order) // 2]), 9, 17}
+    for i in sorted(pick):
+        W = solo[i].W.cpu().numpy()
+        same_tmfg(got[i], oracle.tmfg_lazy(W))
