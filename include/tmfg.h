@@ -162,6 +162,25 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
    compactions; the others read 0. */
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]);
 
+/* ---- A build that allocates nothing ---------------------------------------------- */
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc. Builds one TMFG as tmfg_build does (the
+   same kernels, bit-identical results) with plan flags `flags` (TMFG_NO_VALIDATE,
+   TMFG_RULE_PAPER or TMFG_RULE_CORR_PREFIX(p); TMFG_TIMING is refused with TMFG_E_INVALID),
+   taking its scratch from one fixed device array inside the library instead of a plan:
+   TMFG_NOALLOC_SCRATCH_BYTES bytes on each GPU it runs on, held from the library's loading
+   on that GPU until the process ends. A job fits when tmfg_footprint_bytes(n, L, 0) is at
+   most that size, with L = 2 when the job gives W (for example n <= 2048 for any L <= 2048,
+   n <= 2530 at L = 256); a larger job gets TMFG_E_SIZE before any GPU work. The call
+   allocates no memory; its first call on a device looks up the array's device address.
+   All calls on one GPU share that GPU's array, which keeps the last call's contents (each
+   build writes what it reads first). Calls that overlap on one GPU (different streams, or
+   host threads without ordering) race and give undefined results: order them on one
+   stream. Argument and error behaviour otherwise as tmfg_build. */
+#define TMFG_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+tmfg_status tmfg_build_noalloc(const tmfg_job* job, uint32_t flags, hipStream_t stream);
+
 /* ---- Batches: many independent builds in one graph replay ------------------------ */
 
 /* Prepare `count` builds (the jobs' sizes and buffers are fixed from now on): allocates

@@ -46,6 +46,7 @@ SIGNATURES = {
     "tmfg_plan_destroy": (_I, [_P]),
     "tmfg_footprint_bytes": (ctypes.c_size_t, [_I, _I, ctypes.c_uint32]),
     "tmfg_build": (_I, [_P, _P, _P]),
+    "tmfg_build_noalloc": (_I, [_P, ctypes.c_uint32, _P]),
     "tmfg_plan_phase_ms": (_I, [_P, ctypes.POINTER(ctypes.c_float)]),
     "tmfg_plan_stats": (_I, [_P, ctypes.POINTER(_I)]),
     "tmfg_correlation": (_I, [_P, _P, _I, _I, _P, _P, _P]),

@@ -5,6 +5,7 @@
 #include "internal.h"
 #include "batchplan.h"
 
+#include <mutex>
 #include <new>
 
 namespace {
@@ -371,3 +372,51 @@ tmfg_status tmfg_face_sweep(tmfg_plan plan, const float* W, int32_t n, const int
 
 }  // extern "C"
 
+// ---------------------------------------------------------------------------------------
+// Builds that allocate nothing: the scratch is one fixed array per GPU. In host code the
+// name `scratch` stands for a host-side shadow, not a device address; the device address
+// comes from hipGetSymbolAddress, once per device, and only that address reaches GPU work.
+// ---------------------------------------------------------------------------------------
+static __device__ __align__(256) uint8_t scratch[TMFG_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices];   // device address of `scratch` on each device, or null
+
+tmfg_status scratch_on_current_device(uint8_t** out) {
+  int dev = 0;
+  TMFG_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return TMFG_E_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    TMFG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return TMFG_E_INTERNAL;
+    g_scratch_ptr[dev] = (uint8_t*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return TMFG_OK;
+}
+}  // namespace
+
+extern "C" {
+
+tmfg_status tmfg_build_noalloc(const tmfg_job* job, uint32_t flags, hipStream_t stream) {
+  bool paper = false;
+  int prefix = 0;
+  if ((flags & ~(uint32_t)(TMFG_NO_VALIDATE | tmfg::kRuleFlags)) || !tmfg::rule_from_flags(flags, &paper, &prefix))
+    return TMFG_E_INVALID;
+  const tmfg_status st = check_job(job, tmfg::kMaxN, INT_MAX);
+  if (st != TMFG_OK) return st;
+  const int L = job->X ? job->L : 2;
+  if (carve(nullptr, job->n, L).bytes > TMFG_NOALLOC_SCRATCH_BYTES) return TMFG_E_SIZE;
+  hipError_t e = tmfg::init_attributes_once();
+  if (e != hipSuccess) return hip_fail(e);
+  uint8_t* base = nullptr;
+  const tmfg_status sa = scratch_on_current_device(&base);
+  if (sa != TMFG_OK) return sa;
+  return enqueue_build(carve(base, job->n, L), flags, job, stream, nullptr);
+}
+
+}  // extern "C"

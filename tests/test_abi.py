@@ -189,3 +189,36 @@ def test_batch_footprint_host_side():
     assert xo - w >= n * L * 4                              # the standardised series
     two = fp(job(n), job(500))
     assert two - w >= 6 * 500 * ((499 + 7) // 8 * 8)
+
+
+def test_noalloc_build_host_side_checks():
+    """tmfg_build_noalloc refuses, before any device call, bad flags (TMFG_TIMING among them)
+    and jobs whose scratch would not fit its fixed array; the limit is the plan footprint."""
+    lib = binding.lib()
+    P = 0x1000
+    cap = 64 << 20
+
+    def job(n, L=0, X=False):
+        j = binding.Job()
+        j.n, j.L = n, L
+        j.X, j.W = (P, None) if X else (None, P)
+        j.order = j.edges = j.faces = j.status = j.steps = j.step_gain = P
+        return j
+
+    def call(j, flags=0):
+        return lib.tmfg_build_noalloc(ctypes.byref(j), flags, None)
+
+    assert lib.tmfg_build_noalloc(None, 0, None) == 1
+    assert call(job(100), binding.TIMING) == 1
+    assert call(job(100), binding.RULE_CORR) == 1               # corr-tmfg needs a prefix
+    assert call(job(3)) == 2
+    assert call(job(100, L=1, X=True)) == 2
+    # the largest n that fits at L = 256, and the next one, which must be refused
+    fits = [n for n in range(2400, 2700) if binding.footprint_bytes(n, 256) <= cap]
+    n_top = max(fits)
+    assert n_top >= 2530 and binding.footprint_bytes(2048, 2048) <= cap
+    assert call(job(n_top + 1, L=256, X=True)) == 2
+    assert call(job(20000, L=1024, X=True)) == 2
+    # a W job is sized as L = 2
+    fits_w = max(n for n in range(2400, 2800) if binding.footprint_bytes(n, 2) <= cap)
+    assert call(job(fits_w + 1)) == 2
