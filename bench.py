@@ -8,8 +8,13 @@ white-noise series).
 
 value = whole-job insertions per second = steps * (n-4) / (time of the timed steps).
 Also printed: per-phase times from HIP events on the build stream, the loop-only
-insertion rate, the roofline of the dominant kernel and the CPU oracle timed on a bounded
-sample of the same workload.
+insertion rate, the roofline of the dominant kernel (the insertion loop: its dependent
+trips to memory against the measured latency of one trip), the CPU oracle timed on the
+same workload, and, in the same line, the other two parts of the metric: the batched form
+(512 uneven instances per graph replay, builds/s, autotuned against default launches and
+against one build per launch) and the serving form (p50/p99 latency at 0.5x and 0.8x of
+the saturated rate, against serial plain builds under the same arrivals). Batched and
+served results are checked bitwise against plain builds before their rates are reported.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c3]
 """
@@ -38,9 +43,15 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=512, help="c5: requests one server dispatch groups")
     ap.add_argument("--streams", type=int, default=4, help="c5: server dispatches in flight")
     ap.add_argument("--no-serial", action="store_true", help="c5: skip the serial plain-build comparison")
+    ap.add_argument("--serial-requests", type=int, default=300,
+                    help="c5: requests of the trace (from its start) replayed as serial plain builds")
+    ap.add_argument("--no-c4", action="store_true", help="default run: leave out the batched (c4) summary")
+    ap.add_argument("--no-c5", action="store_true", help="default run: leave out the serving (c5) summary")
+    ap.add_argument("--c4-steps", type=int, default=5, help="default run: timed replays of the c4 batch")
     ap.add_argument("--fifo", action="store_true", help="c5: dispatch strictly in arrival order")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=8000)
+    ap.add_argument("--cpu-sample-steps", type=int, default=0,
+                    help="insertions of the oracle's build to time (0: all of them)")
     ap.add_argument("--rule", default="exact", choices=["exact", "paper", "corr"],
                     help="face rule: exact greedy, the paper's heap rule (Algorithm 2), or corr-tmfg "
                          "with a prefix size (Algorithm 1)")
@@ -145,8 +156,9 @@ def workload(name):
 def cpu_baseline(X: np.ndarray, W_gpu: np.ndarray, sample_steps: int) -> dict:
     """The CPU oracle on the host cores: float64 Pearson of all series (BLAS, all threads),
     float64 seed scores, and the oracle's lazy exact TMFG schedule (oracle.tmfg.tmfg_lazy,
-    single thread) timed for its first `sample_steps` insertions and for none; the
-    difference is the loop's time for those insertions, scaled to n-4."""
+    single thread) timed for its first `sample_steps` insertions (all of them when 0, the
+    default) and for none; the difference is the loop's time for those insertions, scaled
+    to n-4 when it is a sample."""
     import oracle
     from oracle import tmfg as otm
     try:
@@ -158,7 +170,7 @@ def cpu_baseline(X: np.ndarray, W_gpu: np.ndarray, sample_steps: int) -> dict:
     t0 = time.perf_counter()
     oracle.pearson64(X)
     t_pearson = time.perf_counter() - t0
-    k = min(sample_steps, n - 4)
+    k = n - 4 if sample_steps <= 0 else min(sample_steps, n - 4)
     t0 = time.perf_counter()
     otm.tmfg_lazy(W_gpu, max_steps=0)          # checks, seed scores and the four seed faces
     t_setup = time.perf_counter() - t0
@@ -166,39 +178,45 @@ def cpu_baseline(X: np.ndarray, W_gpu: np.ndarray, sample_steps: int) -> dict:
     otm.tmfg_lazy(W_gpu, max_steps=k)
     t_loop = max(time.perf_counter() - t0 - t_setup, 1e-9)
     t_total = t_pearson + t_setup + t_loop * (n - 4) / k
+    if k == n - 4:
+        what = f"all {n - 4} insertions ({t_loop:.2f}s, 1 thread): the whole build, not a sample"
+    else:
+        what = (f"its first {k} of {n - 4} insertions ({t_loop:.2f}s, 1 thread) scaled linearly to all "
+                f"insertions (late insertions cost more, so this overstates the oracle's rate)")
     return {
         "value": (n - 4) / t_total, "unit": "insertions/s", "cores": int(threads), "kind": "oracle",
         "sample": (f"float64 Pearson of all {n} series ({t_pearson:.2f}s, {threads} BLAS threads); the "
-                   f"oracle's lazy exact schedule: checks, seed and seed faces ({t_setup:.2f}s), then its first "
-                   f"{k} of {n - 4} insertions ({t_loop:.2f}s, 1 thread) scaled linearly to all insertions"),
+                   f"oracle's lazy exact schedule: checks, seed and seed faces ({t_setup:.2f}s), then " + what),
     }
 
 
-def bench_batch(args):
+def bench_batch(args, steps=None, warmup=None):
     """512 independent instances (n log-uniform in [64, 4096], L uniform in [64, 512]) in one
     graph replay with autotuned launch configurations, against the same batch with default
-    configurations and against the same instances built one per launch."""
+    configurations and against the same instances built one per launch. Every instance of
+    the autotuned batch is checked bitwise against its plain build before rates are reported."""
     import torch
     import paper_2408_09399_amd as tm
     from paper_2408_09399_amd import synth
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     inst = synth.config_c4(args.batch)
     dev = torch.device("cuda:0")
     Xs = [torch.from_numpy(s.X).to(dev) for s in inst]
     stream = torch.cuda.current_stream()
 
     def timed(batch):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             batch.run(stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             batch.run(stream)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         bad = [i for i, r in enumerate(batch.results) if int(r.status.item()) != 0]
         if bad:
-            print(json.dumps({"error": f"batch instances failed: {bad[:5]}"}))
-            sys.exit(1)
+            raise RuntimeError(f"batch instances failed: {bad[:5]}")
         return wall
 
     rule = rule_flags(tm, args.rule, args.prefix)
@@ -221,26 +239,32 @@ def bench_batch(args):
         tm.build(X=x, plan=plan, out=o, stream=stream)
     torch.cuda.synchronize()
     plain = time.perf_counter() - t0
+    mismatched = [i for i, (g, o) in enumerate(zip(batch.results, outs))
+                  if not all(torch.equal(getattr(g, k), getattr(o, k)) for k in ("order", "edges", "steps", "faces"))
+                  or not torch.equal(g.step_gain.view(torch.int32), o.step_gain.view(torch.int32))]
+    if mismatched:
+        raise RuntimeError(f"batched results differ from plain builds: {mismatched[:5]}")
     insertions = sum(s.X.shape[0] - 4 for s in inst)
-    per = wall / args.steps
+    per = wall / steps
     out = {
         "metric": "batched builds/s (512 uneven instances per graph replay)",
-        "value": round(len(inst) / per, 2), "unit": "builds/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(per * 1e3, 3), "higher_is_better": True,
+        "value": round(len(inst) / per, 2), "unit": "builds/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(per * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{len(inst)} planted-cluster instances, n log-uniform in [64, 4096], "
                                f"L uniform in [64, 512]", "instances": len(inst),
                    "sum_n": int(sum(s.X.shape[0] for s in inst)), "rule": rule_name(args)},
         "insertions_per_s": round(insertions / per, 1),
         "autotuned": tuned_cfg,
-        "default_launch": {"ms_per_step": round(wall_default / args.steps * 1e3, 3),
-                           "builds_per_s": round(len(inst) * args.steps / wall_default, 2)},
+        "default_launch": {"ms_per_step": round(wall_default / steps * 1e3, 3),
+                           "builds_per_s": round(len(inst) * steps / wall_default, 2)},
         "plain_one_per_launch": {"seconds": round(plain, 3), "builds_per_s": round(len(inst) / plain, 2)},
         "speedup_vs_plain": round(plain / per, 2),
+        "checked": f"all {len(inst)} autotuned results bitwise equal to their plain builds",
     }
     plan.close()
     batch.close()
-    print(json.dumps(out))
+    return out
 
 
 def _percentile(v, p):
@@ -285,14 +309,39 @@ def _replay(srv, Xs, t_unit, qps, warm):
     span = (max(r["done_ns"] for r in meas) - min(r["arrival_ns"] for r in meas)) * 1e-9
     return {"p50_ms": round(_percentile(lat, 50), 2), "p99_ms": round(_percentile(lat, 99), 2),
             "mean_ms": round(float(np.mean(lat)), 2), "builds_per_s": round(len(meas) / span, 1),
-            "requests": len(meas)}
+            "requests": len(meas)}, out
+
+
+def _serial_replay(tm, plan, Xs, t_unit, qps, dev):
+    """Plain builds of the requests one at a time in arrival order (each waits for its arrival
+    and for the one before): copy in, build, copy out; latencies observed on the host clock."""
+    import torch
+    outs = []
+    lat = []
+    t0 = time.perf_counter() + 0.02
+    busy = 0.0
+    for i, X in enumerate(Xs):
+        arrival = t0 + t_unit[i] / qps
+        d = arrival - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        s0 = time.perf_counter()
+        res = tm.build(X=torch.from_numpy(X).to(dev), plan=plan)
+        got = res.to_numpy()
+        done = time.perf_counter()
+        busy += done - s0
+        lat.append((done - arrival) * 1e3)
+        outs.append(got)
+    return {"p50_ms": round(_percentile(lat, 50), 2), "p99_ms": round(_percentile(lat, 99), 2),
+            "requests": len(Xs), "builds_per_s": round(len(Xs) / busy, 1)}, outs
 
 
 def bench_serve(args):
     """Serving: Poisson arrivals of rolling-window requests (n log-uniform in [100, 8000],
     L = 256) from host memory through the request server; p50/p99 latency (done - arrival,
-    queueing included) at 0.5x and 0.8x of the saturated rate, against serial plain builds
-    under the same arrival trace."""
+    queueing included) at 0.5x and 0.8x of the saturated rate, against serial plain builds of
+    the start of the same arrival trace at the same rates, observed the same way. The serial
+    builds' results are checked bitwise against the server's before rates are reported."""
     import torch
     import paper_2408_09399_amd as tm
     from paper_2408_09399_amd import synth
@@ -301,46 +350,20 @@ def bench_serve(args):
     Xs = [r.series.X for r in trace]
     t_unit = np.array([r.t_arrival for r in trace])
     n_max = max(X.shape[0] for X in Xs)
+    rule = rule_flags(tm, args.rule, args.prefix)
     srv = tm.Server(hbm_budget=96 << 30, host_budget=4 << 30, max_batch=args.max_batch, n_streams=args.streams,
-                    n_max=n_max, L_max=256, flags=(tm.SERVER_FIFO if args.fifo else 0) |
-                    rule_flags(tm, args.rule, args.prefix))
+                    n_max=n_max, L_max=256, flags=(tm.SERVER_FIFO if args.fifo else 0) | rule)
     _replay(srv, Xs[: warm], t_unit, None, 0)                # first use: code paths, caches
-    sat = _replay(srv, Xs, t_unit, None, 0)                  # everything at once
+    sat, _ = _replay(srv, Xs, t_unit, None, 0)               # everything at once
     rates = {}
+    served = {}
     for f in (0.5, 0.8):
         qps = f * sat["builds_per_s"]
-        r = _replay(srv, Xs, t_unit, qps, warm)
+        r, got = _replay(srv, Xs, t_unit, qps, warm)
         r["qps"] = round(qps, 1)
         rates[f"{f}x"] = r
+        served[f"{f}x"] = got
     srv.close()
-
-    # serial plain builds of the same requests, one at a time in arrival order: service time
-    # = copy in + build + copy out; latency from the single-server queue at each rate
-    if args.no_serial:
-        print(json.dumps({"metric": "p50/p99 latency at fixed QPS (request server, continuous batching)",
-                          "server": {"max_batch": args.max_batch, "n_streams": args.streams,
-                                     "policy": "fifo" if args.fifo else "size classes"}, "rule": rule_name(args),
-                          "saturated": sat, "at_rate": rates}))
-        return
-    dev = torch.device("cuda:0")
-    plan = tm.Plan(n_max, 256, rule_flags(tm, args.rule, args.prefix))
-    service = np.empty(len(Xs))
-    for i, X in enumerate(Xs):
-        t0 = time.perf_counter()
-        res = tm.build(X=torch.from_numpy(X).to(dev), plan=plan)
-        res.to_numpy()
-        service[i] = time.perf_counter() - t0
-    plan.close()
-    serial = {}
-    for key, r in rates.items():
-        arr = t_unit / r["qps"]
-        done = np.empty(len(Xs))
-        free = 0.0
-        for i in range(len(Xs)):
-            free = max(free, arr[i]) + service[i]
-            done[i] = free
-        lat = (done - arr)[warm:] * 1e3
-        serial[key] = {"p50_ms": round(_percentile(lat, 50), 2), "p99_ms": round(_percentile(lat, 99), 2)}
     out = {
         "metric": "p50/p99 latency at fixed QPS (request server, continuous batching)",
         "value": rates["0.5x"]["p99_ms"], "unit": "ms (p99 at 0.5x saturated QPS)", "n_gpus": 1,
@@ -351,9 +374,27 @@ def bench_serve(args):
                    "server": {"max_batch": args.max_batch, "n_streams": args.streams,
                               "policy": "fifo" if args.fifo else "size classes"}, "rule": rule_name(args)},
         "saturated": sat, "at_rate": rates,
-        "serial_plain": {"builds_per_s": round(len(Xs) / float(service.sum()), 1), "at_rate": serial},
     }
-    print(json.dumps(out))
+    if args.no_serial:
+        return out
+    # serial plain builds of the first requests of the trace, at the same rates
+    k = min(args.serial_requests, len(Xs))
+    dev = torch.device("cuda:0")
+    plan = tm.Plan(n_max, 256, rule)
+    serial = {}
+    for key, r in rates.items():
+        res, outs = _serial_replay(tm, plan, Xs[:k], t_unit, r["qps"], dev)
+        for i, (a, b) in enumerate(zip(outs, served[key][:k])):
+            if b["status"] != 0 or a["status"] != 0 or any(not np.array_equal(a[x], b[x])
+                                                          for x in ("order", "edges", "steps", "faces")) \
+                    or a["step_gain"].tobytes() != b["step_gain"].tobytes():
+                raise RuntimeError(f"request {i}: served result differs from its plain build")
+        serial[key] = res
+    plan.close()
+    out["serial_plain"] = {"requests": k, "at_rate": serial,
+                           "note": f"the first {k} requests of the trace, one plain build at a time; "
+                                   f"each result bitwise equal to the server's"}
+    return out
 
 
 def rule_name(args) -> str:
@@ -485,9 +526,11 @@ def main():
     if args.calibration_copy:
         calibration_copy()
     if args.config == "c4":
-        return bench_batch(args)
+        print(json.dumps(bench_batch(args)))
+        return
     if args.config == "c5":
-        return bench_serve(args)
+        print(json.dumps(bench_serve(args)))
+        return
     if args.edge_sums:
         return bench_edge_sums(args)
     if args.dbht:
@@ -541,16 +584,35 @@ def main():
     walk_rounds, gathers = stats[1], stats[11]
     loop_bytes = walk_rounds * 3 * 64 * 6 + gathers * 4
     loop_gbs = loop_bytes / (ph[3] * 1e-3) / 1e9
-    kernels["tmfg_loop"] = ("hbm", loop_gbs, PEAK_HBM_GBS, "GB/s", ph[3])
+    kernels["tmfg_loop"] = ("latency", None, None, None, ph[3])
     dom = max(kernels, key=lambda k: kernels[k][4])
-    b, ach, peak, unit, _ = kernels[dom]
-    traffic = measured_traffic(dom, args.config)
-    roofline = {"kernel": dom, "bound": b, "achieved": round(ach, 3), "peak": peak, "unit": unit,
-                "frac": round(ach / peak, 5), "traffic": None if traffic is None else round(traffic)}
+    floor = latency_floor(tm)
     if dom == "tmfg_loop":
-        # a build runs the loop kernel in stats[24] + 1 launches with row compactions between;
-        # achieved and traffic count the whole build (all launches)
-        roofline["per"] = f"build ({stats[24] + 1} launches, {stats[24]} row compactions between)"
+        # The loop is a serial chain of dependent trips to memory on one CU. Per build it takes
+        # at least: one trip per selection phase (the records of the queued chunks), one per
+        # insertion (the new vertex's row position, advanced during the selection), and two per
+        # round of each phase's deepest walk (list entries, then the similarities they name;
+        # stats[12] sums those rounds). Its roofline is that count of trips against the measured
+        # latency of one: a 64-line gather that hits the L2 (the floor) and one from HBM.
+        trips = stats[3] + (n - 4) + 2 * stats[12]
+        loop_us = ph[3] * 1e3
+        lat = floor["l2_gather_ns"]
+        roofline = {"kernel": "tmfg_loop", "bound": "latency", "achieved": round(trips / loop_us, 4),
+                    "peak": round(1e3 / lat, 4), "unit": "dependent trips/us",
+                    "frac": round(trips * lat * 1e-3 / loop_us, 5),
+                    "traffic": None if (t := measured_traffic("tmfg_loop", args.config)) is None else round(t),
+                    "trips": int(trips), "floor_ms_l2": round(trips * lat * 1e-6, 3),
+                    "floor_ms_hbm": round(trips * floor["hbm_gather_ns"] * 1e-6, 3),
+                    "us_per_phase": round(loop_us / stats[3], 3), "us_per_insertion": round(loop_us / (n - 4), 3),
+                    "trips_per_phase": round(trips / stats[3], 3),
+                    "hbm": {"achieved": round(loop_gbs, 3), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                            "frac": round(loop_gbs / PEAK_HBM_GBS, 6)},
+                    "per": f"build ({stats[24] + 1} launches, {stats[24]} row compactions between)"}
+    else:
+        b, ach, peak, unit, _ = kernels[dom]
+        traffic = measured_traffic(dom, args.config)
+        roofline = {"kernel": dom, "bound": b, "achieved": round(ach, 3), "peak": peak, "unit": unit,
+                    "frac": round(ach / peak, 5), "traffic": None if traffic is None else round(traffic)}
 
     out = {
         "metric": "TMFG insertions/s at n=20k; batched builds/s; p50/p99 latency at fixed QPS",
@@ -577,6 +639,7 @@ def main():
                        "us": {"select": stats[5], "load": stats[6], "walk": stats[7],
                               "sweep": stats[8], "publish": stats[9], "kernel": stats[10]}},
         "roofline": roofline,
+        "latency_floor": floor,
         "face_sweep_refresh": sweep_refresh(tm, plan, res.W, res, n, stream),
     }
     if args.rule == "exact":
@@ -586,7 +649,27 @@ def main():
     if not args.no_cpu_baseline and args.rule == "exact":
         out["cpu_baseline"] = cpu_baseline(s.X, res.W.cpu().numpy(), args.cpu_sample_steps)
     plan.close()
+    del X, res
+    torch.cuda.empty_cache()
+    if args.config == "c3" and not args.no_c4:
+        out["batched_c4"] = bench_batch(args, steps=args.c4_steps, warmup=2)
+        print(json.dumps({"progress": "c4 done", "builds_per_s": out["batched_c4"]["value"]}), file=sys.stderr,
+              flush=True)
+    if args.config == "c3" and not args.no_c5:
+        out["serving_c5"] = bench_serve(args)
     print(json.dumps(out))
+
+
+def latency_floor(tm) -> dict:
+    """Latency of one dependent trip to memory from one wave (tmfg_probe_load_latency): one line
+    or a 64-line gather, from a chain that sits in the L2 and from one that is read from HBM."""
+    kw = dict(steps=20000)
+    return {"l2_line_ns": round(tm.load_latency_ns(1 << 20, lanes=1, **kw), 1),
+            "l2_gather_ns": round(tm.load_latency_ns(1 << 20, lanes=64, **kw), 1),
+            "hbm_line_ns": round(tm.load_latency_ns(4 << 30, lanes=1, **kw), 1),
+            "hbm_gather_ns": round(tm.load_latency_ns(4 << 30, lanes=64, **kw), 1),
+            "method": "one wave, pointer chase, 20000 dependent trips; L2: 1 MiB chain read once untimed "
+                      "first; HBM: 4 GiB chain, every line read once"}
 
 
 if __name__ == "__main__":
