@@ -200,15 +200,8 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
           for (;;) {
             const int qs = (pu & ~7) + lane * 8;
             const uint4 sv = *(const uint4*)(row + min(qs, ldi - 8));
-            const uint32_t wd[4] = {sv.x, sv.y, sv.z, sv.w};
-            int fp = 0x7fffffff;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-              const int id = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-              const int q = qs + j;
-              const bool ok = q >= pu && q < mr && !is_ins(bits, id < n ? id : 0);
-              fp = ok ? min(fp, q) : fp;
-            }
+            const uint32_t mk = open_mask8(bits, sv, n, qs, pu, mr);
+            const int fp = mk ? qs + (int)__builtin_ctz(mk) : 0x7fffffff;
             const int f = wave_min_i32(fp);
             if (f != 0x7fffffff) {
               pu = f;

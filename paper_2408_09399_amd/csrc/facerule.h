@@ -11,6 +11,38 @@ constexpr int kGroup = 16;                       // lanes per face walk
 
 __device__ __forceinline__ bool is_ins(const uint32_t* bits, int u) { return (bits[u >> 5] >> (u & 31)) & 1u; }
 
+// 1 when list entry u at position p, lo <= p < hi, is an uninserted vertex (u >= n: no). The
+// bitmap word is read whatever the position, and the tests are combined without short
+// circuits, so that the reads of many entries are in flight together instead of one trip
+// through the LDS each.
+__device__ __forceinline__ uint32_t open_entry(const uint32_t* bits, int u, int n, int p, int lo, int hi) {
+  const int uc = u < n ? u : 0;
+  const uint32_t w = bits[uc >> 5];
+  return (uint32_t)(p >= lo) & (uint32_t)(p < hi) & (uint32_t)(u < n) & ~(w >> (uc & 31)) & 1u;
+}
+
+// The same for the 8 ids of one 16-byte load (entry j at position q0 + j): bit j of the result.
+// The eight bitmap words are read before any is used (a scheduling barrier keeps them
+// together), so they cost one trip through the LDS instead of eight.
+__device__ __forceinline__ uint32_t open_mask8(const uint32_t* bits, uint4 w8, int n, int q0, int lo, int hi) {
+  const uint32_t wd[4] = {w8.x, w8.y, w8.z, w8.w};
+  int u[8];
+  uint32_t bw[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    u[j] = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+    bw[j] = bits[(u[j] < n ? u[j] : 0) >> 5];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+  uint32_t mask = 0;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int p = q0 + j;
+    mask |= ((uint32_t)(p >= lo) & (uint32_t)(p < hi) & (uint32_t)(u[j] < n) & ~(bw[j] >> (u[j] & 31)) & 1u) << j;
+  }
+  return mask;
+}
+
 __device__ __forceinline__ uint64_t cand_key(float g, int u) {
   return ((uint64_t)ord_f32(g) << 32) | (uint32_t)(0xffff - u);
 }
@@ -68,6 +100,22 @@ __device__ __forceinline__ int group_min_i32(int x) {
   x = min(x, (int)dpp32<kDppXor2>((uint32_t)x));
   if (G >= 8) x = min(x, (int)dpp32<kDppHalfMirror>((uint32_t)x));
   if (G >= 16) x = min(x, (int)dpp32<kDppMirror>((uint32_t)x));
+  return x;
+}
+// Inclusive prefix sum inside each 16-lane row (row_shr by 1, 2, 4, 8; lanes shifted in from
+// outside the row contribute 0).
+__device__ __forceinline__ uint32_t row_scan_u32(uint32_t x) {
+  x += dpp32<0x111>(x);
+  x += dpp32<0x112>(x);
+  x += dpp32<0x114>(x);
+  x += dpp32<0x118>(x);
+  return x;
+}
+__device__ __forceinline__ int group_sum_i32(int x) {
+  x += (int)dpp32<kDppXor1>((uint32_t)x);
+  x += (int)dpp32<kDppXor2>((uint32_t)x);
+  x += (int)dpp32<kDppHalfMirror>((uint32_t)x);
+  x += (int)dpp32<kDppMirror>((uint32_t)x);
   return x;
 }
 __device__ __forceinline__ uint64_t group_max_u64(uint64_t v) { return group_max_u64<kGroup>(v); }
@@ -183,14 +231,13 @@ __device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* i
       int fp = 0x7fffffff;          // (position << 16) | id of the first uninserted entry
 #pragma unroll
       for (int l = 0; l < L; ++l) {
+        const uint32_t mk = open_mask8(bits, sv[t][l], n, qs + 8 * l, pos[t], m);
         const uint32_t wd[4] = {sv[t][l].x, sv[t][l].y, sv[t][l].z, sv[t][l].w};
+        const int j = (int)__builtin_ctz(mk | 0x100u);
+        int u = 0;                  // the id of entry j (selects over constant indices)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-          const int p = qs + 8 * l + j;
-          const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
-          fp = ok ? min(fp, (p << 16) | u) : fp;
-        }
+        for (int jj = 0; jj < 8; ++jj) u = j == jj ? (int)((wd[jj >> 1] >> (16 * (jj & 1))) & 0xffffu) : u;
+        fp = mk ? min(fp, ((qs + 8 * l + j) << 16) | u) : fp;
       }
       const int f = group_min_i32<G>(fp);
       if (f != 0x7fffffff) {

@@ -101,8 +101,6 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
   const int ldi = (int)P.ldi;
   const int x3[3] = {a, b, c};
   const float* Wx[3] = {P.W + (size_t)a * n, P.W + (size_t)b * n, P.W + (size_t)c * n};
-  const uint64_t gmask = ((1ull << kGroup) - 1) << gbase;
-  const uint64_t below = ((1ull << gl) - 1) << gbase;     // lanes of my group before me
   int pos[3], newp[3];
   bool tight[3], skip[3];
 #pragma unroll
@@ -137,14 +135,24 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       iv[t] = *(const uint2*)(P.idx + off);
       vv[t] = *(const float4*)(P.vals + off);
     }
-    // (2) uninserted entries, their ranks, and which are taken this round
+    // (2) uninserted entries, their ranks, and which are taken this round. The inserted
+    //     bits of all twelve entries are read from the LDS before any is used (one trip).
     int id[3][kScan];
     float val[3][kScan];
-    uint32_t um[3], take[3];
+    uint32_t um[3], take[3], insw[3][kScan];
     int seen[3], bl[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const uint32_t wd[2] = {iv[t].x, iv[t].y};
+#pragma unroll
+      for (int j = 0; j < kScan; ++j) {
+        id[t][j] = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        insw[t][j] = bits[(id[t][j] < n ? id[t][j] : 0) >> 5];
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
       val[t][0] = vv[t].x;
       val[t][1] = vv[t].y;
       val[t][2] = vv[t].z;
@@ -152,19 +160,18 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       um[t] = 0;
 #pragma unroll
       for (int j = 0; j < kScan; ++j) {
-        id[t][j] = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+        const int u = id[t][j];
         const int p = q[t] + j;
-        const bool ok = !skip[t] && p >= pos[t] && p < m && !is_ins(bits, id[t][j] < n ? id[t][j] : 0);
-        um[t] |= ok ? (1u << j) : 0u;
+        const uint32_t open = (uint32_t)(p >= pos[t]) & (uint32_t)(p < m) & (uint32_t)(u < n) &
+                              ~(insw[t][j] >> (u & 31)) & (uint32_t)!skip[t] & 1u;
+        um[t] |= open << j;
       }
-      int before = 0;
-      seen[t] = 0;
-#pragma unroll
-      for (int j = 0; j < kScan; ++j) {
-        const uint64_t bj = __ballot((um[t] >> j) & 1u) & gmask;
-        before += __popcll(bj & below);
-        seen[t] += __popcll(bj);
-      }
+      // ranks: an inclusive scan of the lanes' counts over the group by DPP row shifts;
+      // the group total is the scan's maximum
+      const uint32_t cnt = (uint32_t)__popc(um[t]);
+      const uint32_t incl = row_scan_u32(cnt);
+      const int before = (int)(incl - cnt);
+      seen[t] = (int)group_max_u32<kGroup>(incl);
       // the first kCand go to slots t*kCand + rank of the group's buffer; the entry of rank
       // kCand (if any) is the list's bound entry
       bl[t] = -1;
@@ -194,8 +201,12 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       const int t = sl / kCand;
       st[e] = t;
       sok[e] = sl < 3 * kCand && (sl - t * kCand) < (int)(t == 0 ? take[0] : t == 1 ? take[1] : take[2]);
-      su[e] = sok[e] ? (int)gb.cid[sl] : 0;
-      sv[e] = sok[e] ? gb.cval[sl] : 0.0f;
+      // read whatever the slot holds (inside the buffer), then select: no branch around the reads
+      const int slc = sl < 3 * kCand ? sl : 3 * kCand - 1;
+      const int cu = (int)gb.cid[slc];
+      const float cvv = gb.cval[slc];
+      su[e] = sok[e] ? cu : 0;
+      sv[e] = sok[e] ? cvv : 0.0f;
     }
 #pragma unroll
     for (int e = 0; e < kSlots; ++e) {
@@ -218,42 +229,37 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       ng += sok[e] ? 2 : 0;
     }
     TMFG_WT(1);
-    // (4) bounds, next positions, cached starts
+    // (4) bounds, next positions, cached starts. Values move between the group's lanes by
+    //     DPP reductions inside the row, each with one contributing lane or the group
+    //     minimum; everything is computed for every list and then selected, so the whole
+    //     row stays active. A list being skipped this round keeps its state.
     float bound[3];
     bool exhausted = false, skipping = false;
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
-      bound[t] = -INFINITY;
-      if (skip[t]) {
-        skipping = true;
-        continue;
-      }
+      const bool live = !skip[t];
       const int end = (pos[t] & ~(kScan - 1)) + kSpan;
-      if (!tight[t]) {
-        const uint64_t any = __ballot(um[t] != 0) & gmask;
-        if (any) {
-          tight[t] = true;
-          newp[t] = __shfl(q[t] + (int)__builtin_ctz(um[t] | 0x100u), (int)__builtin_ctzll(any), kWave);
-        } else {
-          newp[t] = end < m ? end : m;
-        }
+      const bool big = seen[t] > kCand;
+      // the span's first uninserted position, if any (positions grow with the lane)
+      const int first = group_min_i32(um[t] ? q[t] + (int)__builtin_ctz(um[t]) : 0x7fffffff);
+      // bound entry: the first entry not evaluated (one lane holds it) when more than kCand
+      // were seen, else the last position scanned (the group's last lane)
+      uint32_t kv = 0u, pv = 0u;
+#pragma unroll
+      for (int j = 0; j < kScan; ++j) {
+        const bool mine = big ? bl[t] == j : (gl == kGroup - 1 && j == kScan - 1);
+        kv = mine ? ord_f32(val[t][j]) : kv;
+        pv = (big && bl[t] == j) ? (uint32_t)(q[t] + j) : pv;
       }
-      if (seen[t] > kCand) {
-        // bound: the first entry not evaluated; resume there
-        const uint64_t own = __ballot(bl[t] >= 0) & gmask;
-        const int l = (int)__builtin_ctzll(own);
-        const int j = bl[t] & (kScan - 1);
-        const float bv = (j == 0) ? val[t][0] : (j == 1) ? val[t][1] : (j == 2) ? val[t][2] : val[t][3];
-        bound[t] = __shfl(bv, l, kWave);
-        pos[t] = __shfl(q[t] + j, l, kWave);
-      } else if (end >= m) {
-        exhausted = true;                        // the list is used up: nothing unseen
-        pos[t] = m;
-      } else {
-        bound[t] = __shfl(val[t][kScan - 1], gbase + kGroup - 1, kWave);   // last position scanned
-        pos[t] = end;
-        skip[t] = seen[t] == 0;                  // a fully inserted stretch: scan ahead wide
-      }
+      const uint32_t kb = group_max_u32<kGroup>(kv);
+      const int pb = (int)group_max_u32<kGroup>(pv);
+      skipping |= !live;
+      if (!tight[t]) newp[t] = live ? (first != 0x7fffffff ? first : min(end, m)) : newp[t];
+      tight[t] = tight[t] || (live && first != 0x7fffffff);
+      bound[t] = (live && (big || end < m)) ? unord_f32(kb) : -INFINITY;
+      exhausted |= live && !big && end >= m;         // the list is used up: nothing unseen
+      pos[t] = live ? (big ? pb : min(end, m)) : pos[t];
+      skip[t] = !live || (!big && end < m && seen[t] == 0);   // a fully inserted stretch: scan ahead wide
     }
     k = group_max_u64(k);
     best = k > best ? k : best;
@@ -277,14 +283,8 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
 #pragma unroll
         for (int w = 0; w < kSkipLoads; ++w) {
           const int qs = (pos[t] & ~7) + (w * kGroup + gl) * 8;
-          const uint32_t wd[4] = {sv[w].x, sv[w].y, sv[w].z, sv[w].w};
-#pragma unroll
-          for (int j = 0; j < 8; ++j) {
-            const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-            const int p = qs + j;
-            const bool ok = p >= pos[t] && p < m && !is_ins(bits, u < n ? u : 0);
-            fp = ok ? min(fp, p) : fp;
-          }
+          const uint32_t mk = open_mask8(bits, sv[w], n, qs, pos[t], m);
+          fp = mk ? min(fp, qs + (int)__builtin_ctz(mk)) : fp;
         }
         const int f = group_min_i32(fp);
         const int end = (pos[t] & ~7) + kSkipLoads * kGroup * 8;
@@ -466,15 +466,8 @@ __device__ __forceinline__ void advance_row(const uint16_t* __restrict__ idx, in
   for (;;) {
     const int qs = (p & ~7) + lane * 8;
     const uint4 sv = *(const uint4*)(row + min(qs, ldi - 8));
-    const uint32_t wd[4] = {sv.x, sv.y, sv.z, sv.w};
-    int fp = 0x7fffffff;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int id = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-      const int q = qs + j;
-      const bool ok = q >= p && q < m && !is_ins(bits, id < n ? id : 0);
-      fp = ok ? min(fp, q) : fp;
-    }
+    const uint32_t mk = open_mask8(bits, sv, n, qs, p, m);
+    const int fp = mk ? qs + (int)__builtin_ctz(mk) : 0x7fffffff;
     const int f = wave_min_i32(fp);
     if (f != 0x7fffffff) {
       p = f;
@@ -738,7 +731,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
                            (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
         }
         // per-lane W reads, summed over the group
-        for (int off = kGroup / 2; off >= 1; off >>= 1) gw += __shfl_xor(gw, off, kWave);
+        gw = group_sum_i32(gw);
         if (gl == 0) {
           w.best = best;
           w.sweep = ok ? 0 : 1;
@@ -1156,7 +1149,7 @@ __global__ __launch_bounds__(kCompactBlock) void compact_rows_kernel(uint16_t* _
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int u = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-        keep |= (p + j < m_old && u < n && !is_ins(s_bits, u)) ? (1u << j) : 0u;
+        keep |= open_entry(s_bits, u, n, p + j, 0, m_old) << j;
       }
       // exclusive prefix of the kept counts over the workgroup
       const int c = __popc(keep);
