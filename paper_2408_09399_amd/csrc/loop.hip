@@ -140,14 +140,16 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     int id[3][kScan];
     float val[3][kScan];
     uint32_t um[3], take[3], insw[3][kScan];
-    int seen[3], bl[3];
+    int seen[3], bpos[3];
+    float bval[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const uint32_t wd[2] = {iv[t].x, iv[t].y};
 #pragma unroll
       for (int j = 0; j < kScan; ++j) {
         id[t][j] = (int)((wd[j >> 1] >> (16 * (j & 1))) & 0xffffu);
-        insw[t][j] = bits[(id[t][j] < n ? id[t][j] : 0) >> 5];
+        // entries past the row's end hold 0xffff (masked below): the address stays in the bitmap
+        insw[t][j] = bits[min(id[t][j], n - 1) >> 5];
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -157,15 +159,17 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       val[t][1] = vv[t].y;
       val[t][2] = vv[t].z;
       val[t][3] = vv[t].w;
+      // positions in [pos, m) of this lane's kScan entries: only the group's first lane can
+      // start before pos, and only lanes near the row's end reach m (every entry before m
+      // holds a vertex id below n)
+      const uint32_t full = (1u << kScan) - 1;
+      const uint32_t lo = gl == 0 ? (full << (pos[t] & (kScan - 1))) & full : full;
+      const int room = m - q[t];
+      const uint32_t hi = room >= kScan ? full : room > 0 ? (1u << room) - 1 : 0u;
       um[t] = 0;
 #pragma unroll
-      for (int j = 0; j < kScan; ++j) {
-        const int u = id[t][j];
-        const int p = q[t] + j;
-        const uint32_t open = (uint32_t)(p >= pos[t]) & (uint32_t)(p < m) & (uint32_t)(u < n) &
-                              ~(insw[t][j] >> (u & 31)) & (uint32_t)!skip[t] & 1u;
-        um[t] |= open << j;
-      }
+      for (int j = 0; j < kScan; ++j) um[t] |= (~(insw[t][j] >> (id[t][j] & 31)) & 1u) << j;
+      um[t] &= skip[t] ? 0u : (lo & hi);
       // ranks: an inclusive scan of the lanes' counts over the group by DPP row shifts;
       // the group total is the scan's maximum
       const uint32_t cnt = (uint32_t)__popc(um[t]);
@@ -174,7 +178,10 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       seen[t] = (int)group_max_u32<kGroup>(incl);
       // the first kCand go to slots t*kCand + rank of the group's buffer; the entry of rank
       // kCand (if any) is the list's bound entry
-      bl[t] = -1;
+      // the entry of rank kCand (if any, in one lane) is the list's bound entry: its value and
+      // position are kept
+      bval[t] = 0.0f;
+      bpos[t] = -1;
 #pragma unroll
       for (int j = 0; j < kScan; ++j) {
         const int rank = before + __popc(um[t] & ((1u << j) - 1));
@@ -183,7 +190,9 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
           gb.cid[t * kCand + rank] = (uint16_t)id[t][j];
           gb.cval[t * kCand + rank] = val[t][j];
         }
-        bl[t] = (on && rank == kCand) ? j : bl[t];
+        const bool isb = on && rank == kCand;
+        bval[t] = isb ? val[t][j] : bval[t];
+        bpos[t] = isb ? q[t] + j : bpos[t];
       }
       take[t] = seen[t] < kCand ? seen[t] : kCand;
     }
@@ -244,13 +253,9 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       const int first = group_min_i32(um[t] ? q[t] + (int)__builtin_ctz(um[t]) : 0x7fffffff);
       // bound entry: the first entry not evaluated (one lane holds it) when more than kCand
       // were seen, else the last position scanned (the group's last lane)
-      uint32_t kv = 0u, pv = 0u;
-#pragma unroll
-      for (int j = 0; j < kScan; ++j) {
-        const bool mine = big ? bl[t] == j : (gl == kGroup - 1 && j == kScan - 1);
-        kv = mine ? ord_f32(val[t][j]) : kv;
-        pv = (big && bl[t] == j) ? (uint32_t)(q[t] + j) : pv;
-      }
+      const bool mine = big ? bpos[t] >= 0 : gl == kGroup - 1;
+      const uint32_t kv = mine ? ord_f32(big ? bval[t] : val[t][kScan - 1]) : 0u;
+      const uint32_t pv = (big && bpos[t] >= 0) ? (uint32_t)bpos[t] : 0u;
       const uint32_t kb = group_max_u32<kGroup>(kv);
       const int pb = (int)group_max_u32<kGroup>(pv);
       skipping |= !live;
