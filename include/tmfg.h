@@ -36,8 +36,11 @@
  *     hipError_t is available from tmfg_last_hip_error() on the same host thread.
  *   - A plan is not thread-safe: use one plan per host thread. Calls that share a plan
  *     must be ordered on one stream, since they share the plan's scratch memory.
- *   - Limits: 4 <= n <= 20480 (rows are sorted inside one workgroup's 160 KB LDS and ids
- *     are stored in 16 bits); 2 <= L.
+ *   - Limits: 4 <= n <= 32768 for single builds (vertex and face ids are stored in 16 bits,
+ *     and the 2n - 4 face ids of n = 32768 are the most that fit); 4 <= n <= 20480 for
+ *     batches, servers and corr-tmfg (TMFG_RULE_CORR_PREFIX); 2 <= L. A row of up to 20480
+ *     entries is sorted inside one workgroup's 160 KB LDS, a longer one as two halves that
+ *     are then merged.
  */
 #ifndef TMFG_H_
 #define TMFG_H_
@@ -53,7 +56,7 @@ extern "C" {
 typedef enum {
   TMFG_OK = 0,
   TMFG_E_INVALID = 1,     /* null pointer, both or neither of X and W, bad flags, misaligned buffer */
-  TMFG_E_SIZE = 2,        /* n < 4, n > n_max (or > 20480), L < 2, L > L_max */
+  TMFG_E_SIZE = 2,        /* n < 4, n > n_max (or above the limits below), L < 2, L > L_max */
   TMFG_E_NONFINITE = 3,   /* NaN or Inf in X or W (device-detected) */
   TMFG_E_ASYMMETRIC = 4,  /* W[i][j] and W[j][i] differ in their bits (device-detected) */
   TMFG_E_DEGENERATE = 5,  /* a series with all values equal: no Pearson correlation */
@@ -69,6 +72,9 @@ enum {
   TMFG_TIMING = 1u << 1,        /* record per-phase HIP events (tmfg_plan_phase_ms) */
   TMFG_BATCH_NO_GRAPH = 1u << 2, /* batch: launch the kernels directly instead of a graph */
   TMFG_BATCH_AUTOTUNE = 1u << 3, /* batch: pick launch configurations by timing them at creation */
+  /* 32-bit vertex ids (n above 32768). Declared for the interface but not provided: ids and
+     face ids are 16-bit throughout, and every call given this flag returns TMFG_E_INVALID. */
+  TMFG_IDX32 = 1u << 4,
   /* The paper's candidate-limited face rule and heap schedule (Sections 4.1 and 4.2,
      Algorithm 2) instead of the exact greedy rule, for plans and batches. MaxCorrs[v] is
      the most similar uninserted vertex of v (the first uninserted entry of v's sorted row),
@@ -84,7 +90,8 @@ enum {
      id), keeps for each vertex only the first of its pairs among them, applies the kept pairs
      in that order (the k-th kept pair's split takes the next two face ids in turn), and then
      recomputes, eagerly, every face whose pair vertex was inserted and every new face, against
-     the uninserted set after the whole round. Exclusive with TMFG_RULE_PAPER. */
+     the uninserted set after the whole round. Exclusive with TMFG_RULE_PAPER. Up to n = 20480
+     (each face's pair vertex is kept in LDS). */
   TMFG_RULE_CORR = 1u << 9
 };
 #define TMFG_PREFIX_SHIFT 16
@@ -114,10 +121,14 @@ typedef struct {
 
 /* Create a plan for builds with n <= n_max and L <= L_max on the current HIP device.
    Allocates the scratch (similarity matrix, standardised series, sorted ids, face
-   records, the insertion loop's saved state; see tmfg_footprint_bytes). A plan serves one
-   build at a time: builds on one plan must be ordered (the same stream, or events), since
-   each one rewrites all of the plan's scratch. */
-tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags);
+   records, the insertion loop's saved state, and for n_max > 20481 the row sort's staging
+   area; see tmfg_footprint_bytes). A plan serves one build at a time: builds on one plan
+   must be ordered (the same stream, or events), since each one rewrites all of the plan's
+   scratch. max_jobs (>= 0) is the most jobs tmfg_build_batch accepts on this plan (0: the
+   plan serves single builds only). Flags: TMFG_NO_VALIDATE, TMFG_TIMING, TMFG_RULE_PAPER or
+   TMFG_RULE_CORR_PREFIX(p) (n_max <= 20480); others, TMFG_IDX32 among them, give
+   TMFG_E_INVALID. */
+tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, int32_t max_jobs, uint32_t flags);
 
 /* Release a plan and its scratch. Waits for the plan's outstanding work. NULL is a no-op. */
 tmfg_status tmfg_plan_destroy(tmfg_plan plan);
@@ -211,7 +222,8 @@ tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]);
 size_t tmfg_batch_footprint_bytes(const tmfg_job* jobs, int32_t count, uint32_t flags);
 
 /* One-call form: builds (or reuses, when the job array is the same as the previous call's)
-   a batch kept by the plan, and runs it on `stream`. The plan's n_max does not limit it. */
+   a batch kept by the plan, and runs it on `stream`. The plan's n_max does not limit it;
+   count above the plan's max_jobs gives TMFG_E_SIZE. */
 tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count, hipStream_t stream);
 
 /* ---- Serving: requests from host memory, continuous batching ---------------------- */
@@ -309,7 +321,8 @@ tmfg_status tmfg_correlation(tmfg_plan plan, const float* X, int32_t n, int32_t 
    vals[v*ld + k] = W[v][idx[v*ld + k]] as float32 (-0.0 written as +0.0). ld must be a
    multiple of 8 and at least n-1 rounded up to 8; idx and vals must be 16-byte aligned;
    entries n-1 up to the next multiple of 8 of each row are overwritten (idx 0xffff,
-   vals -inf). */
+   vals -inf). Rows of more than 20480 entries are sorted in the plan's staging area as two
+   halves (columns below n/2 and the rest), then merged. */
 tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* idx, float* vals,
                            int64_t ld, hipStream_t stream);
 

@@ -25,6 +25,7 @@ NO_VALIDATE = 1 << 0
 TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
 BATCH_AUTOTUNE = 1 << 3
+IDX32 = 1 << 4               # declared by the C header; not provided (TMFG_E_INVALID)
 RULE_PAPER = 1 << 8
 RULE_CORR = 1 << 9
 PREFIX_SHIFT = 16
@@ -42,7 +43,7 @@ SERVER_RULE_PAPER = 1 << 1
 _P = ctypes.c_void_p
 _I = ctypes.c_int32
 SIGNATURES = {
-    "tmfg_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, ctypes.c_uint32]),
+    "tmfg_plan_create": (_I, [ctypes.POINTER(_P), _I, _I, _I, ctypes.c_uint32]),
     "tmfg_plan_destroy": (_I, [_P]),
     "tmfg_footprint_bytes": (ctypes.c_size_t, [_I, _I, ctypes.c_uint32]),
     "tmfg_build": (_I, [_P, _P, _P]),
@@ -177,13 +178,14 @@ def footprint_bytes(n_max: int, L_max: int, flags: int = 0) -> int:
 
 
 class Plan:
-    """A plan owns the scratch for builds with n <= n_max and L <= L_max."""
+    """A plan owns the scratch for builds with n <= n_max and L <= L_max; tmfg_build_batch on
+    it accepts up to max_jobs jobs."""
 
-    def __init__(self, n_max: int, L_max: int = 2, flags: int = 0):
+    def __init__(self, n_max: int, L_max: int = 2, flags: int = 0, max_jobs: int = 4096):
         h = ctypes.c_void_p()
-        _check(_lib().tmfg_plan_create(ctypes.byref(h), n_max, L_max, flags), "tmfg_plan_create")
+        _check(_lib().tmfg_plan_create(ctypes.byref(h), n_max, L_max, max_jobs, flags), "tmfg_plan_create")
         self._h = h
-        self.n_max, self.L_max, self.flags = n_max, L_max, flags
+        self.n_max, self.L_max, self.flags, self.max_jobs = n_max, L_max, flags, max_jobs
 
     @property
     def handle(self):

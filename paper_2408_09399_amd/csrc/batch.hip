@@ -51,7 +51,7 @@ namespace tmfg {
 tmfg_status job_scratch_bytes(const tmfg_job& j, size_t* bytes) {
   if ((j.X == nullptr) == (j.W == nullptr)) return TMFG_E_INVALID;
   if (!j.order || !j.edges || !j.faces || !j.status) return TMFG_E_INVALID;
-  if (j.n < kMinN || j.n > kMaxN) return TMFG_E_SIZE;
+  if (j.n < kMinN || j.n > kMaxBatchN) return TMFG_E_SIZE;
   if (j.n > 4 && (!j.steps || !j.step_gain)) return TMFG_E_INVALID;
   if (j.X && j.L < 2) return TMFG_E_SIZE;
   const int n = j.n;

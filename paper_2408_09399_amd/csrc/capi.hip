@@ -77,6 +77,7 @@ struct Scratch {
   uint32_t* dflags;
   int32_t* stats;
   uint8_t* lstate;
+  uint8_t* stage;     // the row sort's staging area (rows longer than one workgroup's LDS), or null
   size_t bytes;
 };
 
@@ -98,6 +99,8 @@ Scratch carve(uint8_t* base, int n, int L) {
   r.dflags = (uint32_t*)take(4);
   r.stats = (int32_t*)take(128);
   r.lstate = take(tmfg::loop_state_bytes(n));
+  const size_t stage = tmfg::sort_stage_bytes(n);
+  r.stage = stage ? take(stage) : nullptr;
   r.bytes = off;
   return r;
 }
@@ -106,7 +109,7 @@ Scratch carve(uint8_t* base, int n, int L) {
 
 struct tmfg_plan_s {
   int device = 0;
-  int n_max = 0, L_max = 0;
+  int n_max = 0, L_max = 0, max_jobs = 0;
   uint32_t flags = 0;
   uint8_t* region = nullptr;    // one allocation holding the scratch below
   Scratch sc{};                 // similarity, standardised series, sorted rows, face records,
@@ -181,7 +184,7 @@ tmfg_status enqueue_build(const Scratch& sc, uint32_t flags, const tmfg_job* job
   TMFG_HIP(tmfg::launch_seed_scores(Wt, n, sc.scores, stream));
   record(timed, 2, stream);
   const int64_t ldi = tmfg::sort_row_stride(n);
-  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, sc.idx, sc.vals, ldi, stream));
+  TMFG_HIP(tmfg::launch_sort_rows(Wt, n, sc.idx, sc.vals, ldi, sc.stage, stream));
   record(timed, 3, stream);
   tmfg::LoopParams P{};
   P.W = Wt;
@@ -237,15 +240,17 @@ size_t tmfg_footprint_bytes(int32_t n_max, int32_t L_max, uint32_t flags) {
   return carve(nullptr, n_max, L_max < 2 ? 2 : L_max).bytes;
 }
 
-tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint32_t flags) {
+tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, int32_t max_jobs, uint32_t flags) {
   if (!plan) return TMFG_E_INVALID;
   *plan = nullptr;
   bool paper = false;
   int prefix = 0;
+  // TMFG_IDX32 (32-bit ids for n above 32768) is declared but not provided
   if ((flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING | tmfg::kRuleFlags)) ||
       !tmfg::rule_from_flags(flags, &paper, &prefix))
     return TMFG_E_INVALID;
-  if (n_max < tmfg::kMinN || n_max > tmfg::kMaxN || L_max < 2) return TMFG_E_SIZE;
+  if (n_max < tmfg::kMinN || n_max > tmfg::kMaxN || L_max < 2 || max_jobs < 0) return TMFG_E_SIZE;
+  if (prefix > 0 && n_max > tmfg::kMaxCorrN) return TMFG_E_SIZE;
   hipError_t e = tmfg::init_attributes_once();
   if (e != hipSuccess) return hip_fail(e);
   tmfg_plan p = new (std::nothrow) tmfg_plan_s();
@@ -260,6 +265,7 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, uint
     p->wall_khz = khz;
   p->n_max = n_max;
   p->L_max = L_max;
+  p->max_jobs = max_jobs;
   p->flags = flags;
   const size_t bytes = carve(nullptr, n_max, L_max).bytes;
   tmfg_status st = alloc((void**)&p->region, bytes);
@@ -299,6 +305,7 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream) 
 
 tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count, hipStream_t stream) {
   if (!plan || !jobs || count <= 0) return TMFG_E_INVALID;
+  if (count > plan->max_jobs) return TMFG_E_SIZE;
   if (!tmfg_batch_matches(plan->batch, jobs, count)) {
     if (plan->batch) {
       tmfg_batch_destroy(plan->batch);
@@ -348,7 +355,7 @@ tmfg_status tmfg_sort_rows(tmfg_plan plan, const float* W, int32_t n, uint16_t* 
   if (!valid_n(n, plan->n_max)) return TMFG_E_SIZE;
   if (ld % 8 != 0 || ld < tmfg::sort_row_stride(n) || ((uintptr_t)idx & 15u) || ((uintptr_t)vals & 15u))
     return TMFG_E_INVALID;
-  TMFG_HIP(tmfg::launch_sort_rows(W, n, idx, vals, ld, stream));
+  TMFG_HIP(tmfg::launch_sort_rows(W, n, idx, vals, ld, plan->sc.stage, stream));
   return TMFG_OK;
 }
 
@@ -407,7 +414,7 @@ tmfg_status tmfg_build_noalloc(const tmfg_job* job, uint32_t flags, hipStream_t 
   int prefix = 0;
   if ((flags & ~(uint32_t)(TMFG_NO_VALIDATE | tmfg::kRuleFlags)) || !tmfg::rule_from_flags(flags, &paper, &prefix))
     return TMFG_E_INVALID;
-  const tmfg_status st = check_job(job, tmfg::kMaxN, INT_MAX);
+  const tmfg_status st = check_job(job, prefix > 0 ? tmfg::kMaxCorrN : tmfg::kMaxN, INT_MAX);
   if (st != TMFG_OK) return st;
   const int L = job->X ? job->L : 2;
   if (carve(nullptr, job->n, L).bytes > TMFG_NOALLOC_SCRATCH_BYTES) return TMFG_E_SIZE;

@@ -7,9 +7,15 @@ namespace tmfg {
 
 constexpr int kWave = 64;
 
-// Limits of the library. Rows are sorted inside one workgroup's LDS (6 bytes per element
-// plus the bucket table), which caps n; vertex and face ids are packed as 16 bits.
-constexpr int kMaxN = 20480;
+// Limits of the library. Vertex and face ids are packed as 16 bits, and the 2n - 4 face ids
+// of n = 32768 vertices are the most that fit. A row of up to kMaxLdsSortN entries is sorted
+// inside one workgroup's LDS (6 bytes per entry plus the digit counters); a longer one as two
+// halves that are then merged. corr-tmfg keeps a 16-bit vertex per face in LDS, and batches
+// sort every row in LDS, so both stop at n = 20480.
+constexpr int kMaxN = 32768;
+constexpr int kMaxLdsSortN = 20480;
+constexpr int kMaxCorrN = 20480;
+constexpr int kMaxBatchN = 20480;
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 workgroup
 constexpr int kMinN = 4;
 

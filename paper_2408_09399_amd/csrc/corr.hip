@@ -35,7 +35,7 @@ namespace {
 constexpr int cBlock = 1024;
 constexpr int cWaves = cBlock / kWave;
 constexpr int cMaxWork = cBlock;                 // faces recomputed per pass, one per thread
-constexpr int cMaxChunks = (2 * kMaxN - 4 + 63) / 64;
+constexpr int cMaxChunks = (2 * kMaxCorrN - 4 + 63) / 64;
 constexpr int cChunkIters = (cMaxChunks + kWave - 1) / kWave;
 constexpr uint16_t kNoVertex = 0xffff;
 constexpr int cGroup = 8;                        // lanes per face pair (a half row)
@@ -561,7 +561,7 @@ hipError_t corr_init_attributes() {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, k);
     if (e != hipSuccess) return e;
-    if (a.sharedSizeBytes + corr_lds_bytes(kMaxN) > (size_t)kLdsBytes) return hipErrorInvalidConfiguration;
+    if (a.sharedSizeBytes + corr_lds_bytes(kMaxCorrN) > (size_t)kLdsBytes) return hipErrorInvalidConfiguration;
     e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(kLdsBytes - a.sharedSizeBytes));
     if (e != hipSuccess) return e;
   }

@@ -22,8 +22,11 @@ hipError_t launch_seed_top4(const double* scores, int n, int32_t* seed4, hipStre
 
 // Per-row order of the other vertices: (W[v][u] desc, u asc); u16 ids, and optionally the
 // float32 similarities in the same order, both with row stride ldi.
-hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s);
+// Rows of more than kMaxLdsSortN entries need a staging area of sort_stage_bytes(n) bytes.
+hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, void* stage,
+                            hipStream_t s);
 int64_t sort_row_stride(int n);
+size_t sort_stage_bytes(int n);
 
 // Exact best vertex of many faces by a full sweep of their three rows.
 hipError_t launch_face_sweep(const float* W, int n, const int32_t* faces, int nfaces, const uint32_t* inserted,

@@ -61,8 +61,10 @@ constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
 static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
 static_assert(kMaxWork <= kBlock, "one thread publishes each recomputed face");
 // 64-face chunks of the largest build, and the chunk maxima each lane of a wave covers
-constexpr int kMaxChunks = (2 * kMaxN - 4 + 63) / 64;
-constexpr int kChunkIters = (kMaxChunks + kWave - 1) / kWave;
+// 64-face chunks of a build and the chunk maxima each lane of a wave covers: the loop is
+// compiled for two bounds, up to n = 20480 (batches and most builds) and up to kMaxN
+constexpr int chunk_iters(int n_max) { return ((2 * n_max - 4 + 63) / 64 + kWave - 1) / kWave; }
+constexpr int kItersSmall = chunk_iters(kMaxBatchN), kItersBig = chunk_iters(kMaxN);
 // Time the sub-steps of one walk group (stats [16..19]); the waits it adds slow that group.
 constexpr bool kWalkDiag = false;
 
@@ -199,44 +201,27 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     TMFG_WT(0);
-    // (3) evaluate the staged candidates, kSlots per lane (two at kCand = 8); the two similarities not
-    //     carried by the list are read from W, all loads issued before any is used
-    int su[kSlots], st[kSlots];
-    float sv[kSlots], sw[kSlots][2];
-    bool sok[kSlots];
-#pragma unroll
-    for (int e = 0; e < kSlots; ++e) {
-      const int sl = gl + e * kGroup;
-      const int t = sl / kCand;
-      st[e] = t;
-      sok[e] = sl < 3 * kCand && (sl - t * kCand) < (int)(t == 0 ? take[0] : t == 1 ? take[1] : take[2]);
-      // read whatever the slot holds (inside the buffer), then select: no branch around the reads
-      const int slc = sl < 3 * kCand ? sl : 3 * kCand - 1;
-      const int cu = (int)gb.cid[slc];
-      const float cvv = gb.cval[slc];
-      su[e] = sok[e] ? cu : 0;
-      sv[e] = sok[e] ? cvv : 0.0f;
-    }
-#pragma unroll
-    for (int e = 0; e < kSlots; ++e) {
-      const int t = st[e];
-      const float* o1 = t == 0 ? Wx[1] : Wx[0];
-      const float* o2 = t == 2 ? Wx[1] : Wx[2];
-      sw[e][0] = o1[su[e]];
-      sw[e][1] = o2[su[e]];
-    }
-    uint64_t k = 0;
-#pragma unroll
-    for (int e = 0; e < kSlots; ++e) {
-      const int t = st[e];
-      float w0, w1, w2;
-      if (t == 0) { w0 = sv[e]; w1 = sw[e][0]; w2 = sw[e][1]; }
-      else if (t == 1) { w0 = sw[e][0]; w1 = sv[e]; w2 = sw[e][1]; }
-      else { w0 = sw[e][0]; w1 = sw[e][1]; w2 = sv[e]; }
-      const uint64_t kt = cand_key((w0 + w1) + w2, su[e]);
-      k = (sok[e] && kt > k) ? kt : k;
-      ng += sok[e] ? 2 : 0;
-    }
+    // (3) evaluate the staged candidates, two per lane: lane gl takes slot gl (list a if
+    //     gl < 8, else list b) and slot 16 + gl (list c, lanes gl < 8). The two similarities not
+    //     carried by the list are read from W, all loads issued before any is used. The
+    //     gain keeps the order ((W[a][u] + W[b][u]) + W[c][u]); for a candidate of list a or
+    //     b the first sum is the list's own value plus the other of a, b (addition commutes).
+    static_assert(kCand == 8 && kGroup == 16 && kSlots == 2, "the slot layout below");
+    const bool second = gl >= kCand;                  // slot gl holds a list-b candidate
+    const bool ok0 = (gl & (kCand - 1)) < (int)(second ? take[1] : take[0]);
+    const bool ok1 = !second && gl < (int)take[2];
+    const int slc1 = second ? 3 * kCand - 1 : 2 * kCand + gl;   // a slot inside the buffer
+    const int cu0 = (int)gb.cid[gl], cu1 = (int)gb.cid[slc1];
+    const float cv0 = gb.cval[gl], cv1 = gb.cval[slc1];
+    const int u0 = ok0 ? cu0 : 0, u1 = ok1 ? cu1 : 0;
+    const float wo0 = (second ? Wx[0] : Wx[1])[u0];   // the other of a, b
+    const float wc0 = Wx[2][u0];
+    const float wa1 = Wx[0][u1], wb1 = Wx[1][u1];
+    const uint64_t k0 = cand_key((cv0 + wo0) + wc0, u0);
+    const uint64_t k1 = cand_key((wa1 + wb1) + cv1, u1);
+    uint64_t k = ok0 ? k0 : 0;
+    k = (ok1 && k1 > k) ? k1 : k;
+    ng += (ok0 ? 2 : 0) + (ok1 ? 2 : 0);
     TMFG_WT(1);
     // (4) bounds, next positions, cached starts. Values move between the group's lanes by
     //     DPP reductions inside the row, each with one contributing lane or the group
@@ -401,11 +386,12 @@ __device__ __forceinline__ uint4 make_rec(const Work& w) { return face_record(w.
 // stale and ranks above `floor`, other than chunks c1 and c2 (already listed). The lane holds
 // the maxima of chunks lane + i * kWave (key words khi/klo, inserted flags in insm). Returns
 // the new length, at most kMaxSel.
-__device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uint32_t (&klo)[kChunkIters],
+template <int CI>
+__device__ int append_stale_chunks(const uint32_t (&khi)[CI], const uint32_t (&klo)[CI],
                                    uint32_t insm, int nchunk, uint64_t floor, int c1, int c2, int* sel, int cnt,
                                    int lane) {
 #pragma unroll
-  for (int i = 0; i < kChunkIters; ++i) {
+  for (int i = 0; i < CI; ++i) {
     const int ch = lane + i * kWave;
     const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
     const bool pick = ch < nchunk && ch != c1 && ch != c2 && k > floor && ((insm >> i) & 1u);
@@ -424,12 +410,13 @@ __device__ int append_stale_chunks(const uint32_t (&khi)[kChunkIters], const uin
 // *rest receives the largest maximum of the others (0 if none), the same in every lane: no
 // record of an unlisted chunk ranks above it. Returns the new length.
 constexpr int kPaperChunks = 4;
-__device__ int pick_top_stale_chunks(const uint32_t (&khi)[kChunkIters], const uint32_t (&klo)[kChunkIters],
+template <int CI>
+__device__ int pick_top_stale_chunks(const uint32_t (&khi)[CI], const uint32_t (&klo)[CI],
                                      uint32_t insm, int nchunk, uint64_t floor, int c1, int c2, int* sel, int cnt,
                                      int lane, uint64_t* rest) {
   uint32_t cm = 0;                       // this lane's candidate chunks, by i
 #pragma unroll
-  for (int i = 0; i < kChunkIters; ++i) {
+  for (int i = 0; i < CI; ++i) {
     const int ch = lane + i * kWave;
     const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
     cm |= (ch < nchunk && ch != c1 && ch != c2 && k > floor && ((insm >> i) & 1u)) ? (1u << i) : 0u;
@@ -439,7 +426,7 @@ __device__ int pick_top_stale_chunks(const uint32_t (&khi)[kChunkIters], const u
   auto local_max = [&]() {
     lm = 0;
 #pragma unroll
-    for (int i = 0; i < kChunkIters; ++i) {
+    for (int i = 0; i < CI; ++i) {
       const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
       const bool c = ((cm >> i) & 1u) && k > lm;
       lm = c ? k : lm;
@@ -503,7 +490,7 @@ __device__ __forceinline__ uint64_t clock_ticks() { return wall_clock64(); }
 // that was not recomputed; a pair not committed keeps its old record. This is the order in
 // which the heap would pop them. The top record of a phase that finds a stale maximum is
 // always recomputed and committed, so every such phase makes progress.
-template <bool Paper>
+template <bool Paper, int CI>
 __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ Work work[kMaxWork];
   __shared__ int sel[kMaxSel];
@@ -850,25 +837,25 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       // Every chunk maximum this lane covers is read once (all loads in flight together),
       // then the inserted bits of their vertices; the top record, the best fresh one, the
       // floor after an insertion and the stale chunks to reload all come from these.
-      uint32_t khi[kChunkIters], klo[kChunkIters];
+      uint32_t khi[CI], klo[CI];
       uint32_t insm = 0;
       // the lane index is made opaque here so that the chunk addresses below are formed anew
       // each phase rather than held in registers across the whole loop
       int sl_lane = lane;
       asm volatile("" : "+v"(sl_lane));
 #pragma unroll
-      for (int i = 0; i < kChunkIters; ++i) {
+      for (int i = 0; i < CI; ++i) {
         const int ch = sl_lane + i * kWave;
         const uint4 r = cmax[ch < LL.nchunk ? ch : 0];
         khi[i] = ch < LL.nchunk ? r.x : 0u;
         klo[i] = ch < LL.nchunk ? r.y : 0u;
       }
 #pragma unroll
-      for (int i = 0; i < kChunkIters; ++i)
+      for (int i = 0; i < CI; ++i)
         insm |= is_ins(bits, (int)(klo[i] & 0xffffu)) ? (1u << i) : 0u;
       uint64_t k1 = 0, kf = 0;
 #pragma unroll
-      for (int i = 0; i < kChunkIters; ++i) {
+      for (int i = 0; i < CI; ++i) {
         const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
         k1 = max64(k1, k);
         kf = ((insm >> i) & 1u) ? kf : max64(kf, k);
@@ -923,11 +910,11 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         uint64_t kf2 = ~0ull;
         if (ins + 1 < n) {
 #pragma unroll
-          for (int i = 0; i < kChunkIters; ++i)
+          for (int i = 0; i < CI; ++i)
             if ((klo[i] & 0xffffu) == (uint32_t)u) insm |= 1u << i;
           kf2 = 0;
 #pragma unroll
-          for (int i = 0; i < kChunkIters; ++i) {
+          for (int i = 0; i < CI; ++i) {
             const uint64_t k = ((uint64_t)khi[i] << 32) | klo[i];
             kf2 = ((insm >> i) & 1u) ? kf2 : max64(kf2, k);
           }
@@ -1025,10 +1012,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   }
 }
 
-template <bool Paper>
+template <bool Paper, int CI>
 __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  run_loop<Paper>(P, smem);
+  run_loop<Paper, CI>(P, smem);
 }
 
 // Batched form: persistent workgroups take instances, largest first, from a shared counter;
@@ -1070,7 +1057,7 @@ __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __re
     P.resume = 0;
     P.state = nullptr;
     P.max_rounds = max_rounds;
-    run_loop<Paper>(P, smem);
+    run_loop<Paper, kItersSmall>(P, smem);
     __syncthreads();
   }
 }
@@ -1084,7 +1071,8 @@ hipError_t batch_loop_occupancy(int* per_cu, int n_max, bool paper) {
 }
 
 hipError_t loop_init_attributes() {
-  const void* ks[4] = {(const void*)tmfg_loop_kernel<false>, (const void*)tmfg_loop_kernel<true>,
+  const void* ks[6] = {(const void*)tmfg_loop_kernel<false, kItersSmall>, (const void*)tmfg_loop_kernel<true, kItersSmall>,
+                       (const void*)tmfg_loop_kernel<false, kItersBig>, (const void*)tmfg_loop_kernel<true, kItersBig>,
                        (const void*)batch_loop_kernel<false>, (const void*)batch_loop_kernel<true>};
   for (const void* k : ks) {
     hipFuncAttributes a;
@@ -1231,10 +1219,16 @@ hipError_t launch_loop_compacting(LoopParams p, uint16_t* idx, float* vals, hipS
 
 hipError_t launch_loop(const LoopParams& p, hipStream_t s) {
   const size_t lds = loop_lds_bytes(p.n);
-  if (p.paper)
-    hipLaunchKernelGGL(tmfg_loop_kernel<true>, dim3(1), dim3(kBlock), lds, s, p);
+  // the chunk maxima of n vertices fit the smaller register layout up to n = 20480
+  const bool small = chunk_iters(p.n) <= kItersSmall;
+  if (p.paper && small)
+    hipLaunchKernelGGL((tmfg_loop_kernel<true, kItersSmall>), dim3(1), dim3(kBlock), lds, s, p);
+  else if (p.paper)
+    hipLaunchKernelGGL((tmfg_loop_kernel<true, kItersBig>), dim3(1), dim3(kBlock), lds, s, p);
+  else if (small)
+    hipLaunchKernelGGL((tmfg_loop_kernel<false, kItersSmall>), dim3(1), dim3(kBlock), lds, s, p);
   else
-    hipLaunchKernelGGL(tmfg_loop_kernel<false>, dim3(1), dim3(kBlock), lds, s, p);
+    hipLaunchKernelGGL((tmfg_loop_kernel<false, kItersBig>), dim3(1), dim3(kBlock), lds, s, p);
   return hipGetLastError();
 }
 

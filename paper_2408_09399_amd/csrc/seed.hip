@@ -12,8 +12,8 @@ namespace tmfg {
 // One thread sums column v, which equals row v because W is bitwise symmetric; adjacent
 // threads read adjacent addresses, so each row of W is read once, coalesced. Loads run a
 // block ahead of the sequential float64 additions.
+template <int U>
 __device__ void seed_column(const float* __restrict__ W, int n, double* __restrict__ scores, int v) {
-  constexpr int U = 32;
   const float* col = W + v;
   double acc = 0.0;
   float cur[U], nxt[U];
@@ -40,10 +40,64 @@ __device__ void seed_column(const float* __restrict__ W, int n, double* __restri
   scores[v] = acc;
 }
 
+// Single builds with n a multiple of 4: one thread per row v, adding W[v][u] over u in index
+// order (the definition itself, with no use of symmetry), one wave per 64 rows. Each lane
+// reads its row front to back with 16-byte loads, kSeedDepth blocks of kSeedQuads loads in
+// flight; a load serves one lane, so a wave's load touches 64 lines that the lanes' next
+// loads reuse, and every row is read once, sequentially.
+constexpr int kSeedBlock = 64, kSeedDepth = 4, kSeedQuads = 8;
+static_assert(kSeedDepth * kSeedQuads <= 63, "the loads in flight fit the wave's load counter");
+__global__ __launch_bounds__(kSeedBlock) void seed_rows_kernel(const float* __restrict__ W, int n,
+                                                               double* __restrict__ scores) {
+  const int v = blockIdx.x * kSeedBlock + threadIdx.x;
+  if (v >= n) return;
+  const float4* row = (const float4*)(W + (size_t)v * n);
+  const int nq = n / 4;
+  float4 buf[kSeedDepth][kSeedQuads];
+  // blocks past the row read its last quad (a valid address; the values are never added);
+  // loads are issued whatever the block, so every step has the same count in flight
+  auto issue = [&](int b, float4 (&x)[kSeedQuads]) {
+#pragma unroll
+    for (int k = 0; k < kSeedQuads; ++k) {
+      const int q = b * kSeedQuads + k;
+      x[k] = row[q < nq ? q : nq - 1];
+    }
+  };
+  double acc = 0.0;
+  auto add = [&](int b, const float4 (&x)[kSeedQuads]) {
+#pragma unroll
+    for (int k = 0; k < kSeedQuads; ++k) {
+      const int u = 4 * (b * kSeedQuads + k);
+      const bool in = u < n;
+      acc += (!in || u == v) ? 0.0 : (double)x[k].x;
+      acc += (!in || u + 1 == v) ? 0.0 : (double)x[k].y;
+      acc += (!in || u + 2 == v) ? 0.0 : (double)x[k].z;
+      acc += (!in || u + 3 == v) ? 0.0 : (double)x[k].w;
+    }
+  };
+  const int nb = (nq + kSeedQuads - 1) / kSeedQuads;
+#pragma unroll
+  for (int d = 0; d < kSeedDepth; ++d) issue(d, buf[d]);
+  int b0 = 0;
+  for (; b0 + kSeedDepth <= nb; b0 += kSeedDepth) {
+#pragma unroll
+    for (int d = 0; d < kSeedDepth; ++d) {
+      add(b0 + d, buf[d]);
+      issue(b0 + d + kSeedDepth, buf[d]);
+    }
+  }
+#pragma unroll
+  for (int d = 0; d < kSeedDepth; ++d)
+    if (b0 + d < nb) add(b0 + d, buf[d]);
+  scores[v] = acc;
+}
+
+// Other n: one thread per column (equal to the row: W is bitwise symmetric), adjacent
+// threads on adjacent addresses.
 __global__ __launch_bounds__(256) void seed_scores_kernel(const float* __restrict__ W, int n,
                                                           double* __restrict__ scores) {
   const int v = blockIdx.x * 256 + threadIdx.x;
-  if (v < n) seed_column(W, n, scores, v);
+  if (v < n) seed_column<32>(W, n, scores, v);
 }
 
 // Top-4 by (score desc, id asc), one 256-thread workgroup.
@@ -140,7 +194,7 @@ __global__ __launch_bounds__(256) void batch_seed_kernel(const BatchJob* __restr
   if (unit >= total) return;
   const int i = find_unit(prefix, nlist, unit);
   const BatchJob& J = jobs[list[i]];
-  seed_column(J.W, J.n, J.scores, unit - prefix[i]);
+  seed_column<32>(J.W, J.n, J.scores, unit - prefix[i]);
 }
 
 __global__ __launch_bounds__(256) void batch_validate_kernel(const BatchJob* __restrict__ jobs,
@@ -158,7 +212,11 @@ __global__ __launch_bounds__(256) void batch_validate_kernel(const BatchJob* __r
 }
 
 hipError_t launch_seed_scores(const float* W, int n, double* scores, hipStream_t s) {
-  hipLaunchKernelGGL(seed_scores_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, n, scores);
+  if (n % 4 == 0)
+    hipLaunchKernelGGL(seed_rows_kernel, dim3((n + kSeedBlock - 1) / kSeedBlock), dim3(kSeedBlock), 0, s, W, n,
+                       scores);
+  else
+    hipLaunchKernelGGL(seed_scores_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, n, scores);
   return hipGetLastError();
 }
 

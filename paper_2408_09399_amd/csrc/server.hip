@@ -316,7 +316,7 @@ tmfg_status tmfg_server_create(tmfg_server* out, const tmfg_server_config* cfg) 
       (cfg->flags & ~(uint32_t)(TMFG_SERVER_FIFO | TMFG_SERVER_RULE_PAPER | tmfg::kRuleFlags)) ||
       !tmfg::rule_from_flags(server_rule_flags(cfg->flags), &paper, &prefix))
     return TMFG_E_INVALID;
-  if (cfg->n_max < tmfg::kMinN || cfg->n_max > tmfg::kMaxN || cfg->L_max < 2) return TMFG_E_SIZE;
+  if (cfg->n_max < tmfg::kMinN || cfg->n_max > tmfg::kMaxBatchN || cfg->L_max < 2) return TMFG_E_SIZE;
   hipError_t e = tmfg::init_attributes_once();
   if (e != hipSuccess) return fail(e);
   tmfg_server s = new (std::nothrow) tmfg_server_s();

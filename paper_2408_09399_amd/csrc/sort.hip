@@ -32,6 +32,11 @@ constexpr int kPasses = 4;
 constexpr int kDigits = 256;
 constexpr int kHistStride = kDigits + 1;        // per-wave counters, padded against bank conflicts
 constexpr uint32_t kPadKey = 0xff800000u;       // ~ord(-inf): above every finite key
+// The two-run sort of rows longer than kMaxLdsSortN entries: kStageRows rows staged at a time,
+// each half of a row sorted by one workgroup of kHalfBlock threads, kHalfEpt slots each.
+constexpr int kStageRows = 1024;
+constexpr int kHalfBlock = 1024, kHalfEpt = 16;
+static_assert(kHalfBlock * kHalfEpt >= (kMaxN + 1) / 2, "a run of half a row fits one workgroup");
 
 __device__ __forceinline__ void lds_barrier() {
   // LDS traffic only: a workgroup barrier that does not wait for global loads in flight
@@ -48,48 +53,56 @@ struct RowSort {
   }
 };
 
-// Global loads of one row into registers (raw similarities, position order).
+// A run of one row to sort: the columns j in [c0, c0 + len + skip) other than v (skip is 1
+// when v lies in that range), in ascending j. A whole row is c0 = 0, len = n - 1.
+struct Run {
+  int v, c0, len;
+};
+__device__ __forceinline__ int run_column(const Run& r, int p) {
+  const int j = r.c0 + p;
+  return (r.v >= r.c0 && j >= r.v) ? j + 1 : j;
+}
+
+// Global loads of one run into registers (raw similarities, position order).
 template <int BLOCK, int EPT>
-__device__ __forceinline__ void load_row(const float* __restrict__ W, int n, int v, float (&raw)[EPT]) {
-  const int m = n - 1;
+__device__ __forceinline__ void load_row(const float* __restrict__ W, int n, const Run& r, float (&raw)[EPT]) {
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-  const float* row = W + (size_t)v * n;
-  // slots past the row read the row's last element (a valid address; the value is unused),
+  const float* row = W + (size_t)r.v * n;
+  // slots past the run read the row's last element (a valid address; the value is unused),
   // so that every load is unconditional
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int p = wave * RowSort<BLOCK, EPT>::WS + e * kWave + lane;
-    const int j = p < v ? p : p + 1;
-    raw[e] = row[j < m ? j : m];
+    const int j = run_column(r, p);
+    raw[e] = row[j < n - 1 ? j : n - 1];
   }
 }
 
-// Keys and ids of one row from its similarities (position order).
+// Keys and ids of one run from its similarities (position order).
 template <int BLOCK, int EPT>
-__device__ __forceinline__ void row_keys(const float (&raw)[EPT], int n, int v, uint32_t (&key)[EPT],
+__device__ __forceinline__ void row_keys(const float (&raw)[EPT], const Run& r, uint32_t (&key)[EPT],
                                          uint32_t (&idp)[EPT]) {
-  const int m = n - 1;
   const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
 #pragma unroll
   for (int e = 0; e < EPT; ++e) {
     const int p = wave * RowSort<BLOCK, EPT>::WS + e * kWave + lane;
-    const int j = p < v ? p : p + 1;
-    // branch-free select: slots past the row get the padding key and id
-    const uint32_t in = 0u - (uint32_t)(p < m);
+    const int j = run_column(r, p);
+    // branch-free select: slots past the run get the padding key and id
+    const uint32_t in = 0u - (uint32_t)(p < r.len);
     key[e] = (~ord_f32(raw[e]) & in) | (kPadKey & ~in);
     idp[e] = ((uint32_t)j & in) | (0xffffu & ~in);
   }
 }
 
-// Sorts one row given as keys and ids (idp: id in the low 16 bits) and writes ids (and
-// values) out.
+// Sorts one run given as keys and ids (idp: id in the low 16 bits) and writes its ids (and
+// values) to dst_idx / dst_vals, padded to a multiple of 8 entries (ids 0xffff, values -inf).
 template <int BLOCK, int EPT>
-__device__ __forceinline__ void sort_row_keys(uint32_t (&key)[EPT], uint32_t (&idp)[EPT], int n, int v, uint16_t* __restrict__ idx,
-                              float* __restrict__ vals, int64_t ldi, uint8_t* smem) {
+__device__ __forceinline__ void sort_row_keys(uint32_t (&key)[EPT], uint32_t (&idp)[EPT], int len,
+                                              uint16_t* __restrict__ dst_idx, float* __restrict__ dst_vals,
+                                              uint8_t* smem) {
   using RS = RowSort<BLOCK, EPT>;
   constexpr int NW = RS::NW, CAP = RS::CAP, WS = RS::WS;
-  const int m = n - 1;
-  const int m_al = (m + 7) & ~7;
+  const int m_al = (len + 7) & ~7;
   const int tid = threadIdx.x, lane = tid % kWave, wave = tid / kWave;
   uint32_t* bkey = (uint32_t*)smem;                         // CAP
   uint16_t* bid = (uint16_t*)(bkey + CAP);                  // CAP
@@ -177,11 +190,11 @@ __device__ __forceinline__ void sort_row_keys(uint32_t (&key)[EPT], uint32_t (&i
   }
 
   // 4. write out: ids with 16-byte stores, values (-0.0 already +0.0) beside them
-  uint4* dst = (uint4*)(idx + (size_t)v * ldi);
+  uint4* dst = (uint4*)dst_idx;
   const uint4* src = (const uint4*)bid;
   for (int i = tid; i < m_al / 8; i += BLOCK) dst[i] = src[i];
-  if (vals) {
-    float4* vdst = (float4*)(vals + (size_t)v * ldi);
+  if (dst_vals) {
+    float4* vdst = (float4*)dst_vals;
     for (int i = tid; i < m_al / 4; i += BLOCK) {
       const uint4 k = ((const uint4*)bkey)[i];
       vdst[i] = make_float4(unord_f32(~k.x), unord_f32(~k.y), unord_f32(~k.z), unord_f32(~k.w));
@@ -201,11 +214,95 @@ __global__ __launch_bounds__(BLOCK) void sort_rows_kernel(const float* __restric
   float raw[EPT];
   uint32_t key[EPT], idp[EPT];
   int v = blockIdx.x;
-  if (v < n) load_row<BLOCK, EPT>(W, n, v, raw);
+  if (v < n) load_row<BLOCK, EPT>(W, n, Run{v, 0, n - 1}, raw);
   for (; v < n; v += gridDim.x) {
-    row_keys<BLOCK, EPT>(raw, n, v, key, idp);
-    if (v + (int)gridDim.x < n) load_row<BLOCK, EPT>(W, n, v + gridDim.x, raw);
-    sort_row_keys<BLOCK, EPT>(key, idp, n, v, idx, vals, ldi, smem);
+    row_keys<BLOCK, EPT>(raw, Run{v, 0, n - 1}, key, idp);
+    if (v + (int)gridDim.x < n) load_row<BLOCK, EPT>(W, n, Run{v + (int)gridDim.x, 0, n - 1}, raw);
+    sort_row_keys<BLOCK, EPT>(key, idp, n - 1, idx + (size_t)v * ldi, vals ? vals + (size_t)v * ldi : nullptr, smem);
+  }
+}
+
+// Rows longer than one workgroup's LDS sorts at once (n - 1 > kMaxLdsSortN): each row of a
+// block of `rows` rows from v0 is sorted as two runs, the columns [0, h) and [h, n) without
+// v, each by the LDS radix sort above, into a staging area (run s of local row r at
+// stage + (2r + s) * ldh); merge_halves_kernel then merges the two runs.
+template <int BLOCK, int EPT>
+__global__ __launch_bounds__(BLOCK) void sort_halves_kernel(const float* __restrict__ W, int n, int h, int v0,
+                                                            int rows, uint16_t* __restrict__ st_idx,
+                                                            float* __restrict__ st_vals, int64_t ldh) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  float raw[EPT];
+  uint32_t key[EPT], idp[EPT];
+  auto run_of = [&](int u) {
+    const int v = v0 + (u >> 1), half = u & 1;
+    const int c0 = half ? h : 0, c1 = half ? n : h;
+    return Run{v, c0, (c1 - c0) - ((v >= c0 && v < c1) ? 1 : 0)};
+  };
+  const int units = 2 * rows;
+  int u = blockIdx.x;
+  if (u < units) load_row<BLOCK, EPT>(W, n, run_of(u), raw);
+  for (; u < units; u += gridDim.x) {
+    const Run r = run_of(u);
+    row_keys<BLOCK, EPT>(raw, r, key, idp);
+    if (u + (int)gridDim.x < units) load_row<BLOCK, EPT>(W, n, run_of(u + gridDim.x), raw);
+    sort_row_keys<BLOCK, EPT>(key, idp, r.len, st_idx + (size_t)u * ldh, st_vals + (size_t)u * ldh, smem);
+  }
+}
+
+// Merge of the two sorted runs of each staged row (one workgroup per row, grid-stride). Every
+// id of the first run is below every id of the second, so on equal values the first run's
+// entry goes first: the merged row is in (value desc, id asc) order. The runs' values are
+// held in LDS; each thread finds where its share of the output starts by a binary search on
+// the merge path, then merges its share sequentially.
+constexpr int kMergeBlock = 1024;
+__global__ __launch_bounds__(kMergeBlock) void merge_halves_kernel(const uint16_t* __restrict__ st_idx,
+                                                                  const float* __restrict__ st_vals, int64_t ldh,
+                                                                  int n, int h, int v0, int rows,
+                                                                  uint16_t* __restrict__ idx, float* __restrict__ vals,
+                                                                  int64_t ldi) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+  float* sv = (float*)smem;                  // run A's values, then run B's
+  const int m = n - 1, m_al = (m + 7) & ~7;
+  const int tid = threadIdx.x;
+  const int per = (m + kMergeBlock - 1) / kMergeBlock;
+  for (int r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int v = v0 + r;
+    const int a = h - (v < h ? 1 : 0), b = m - a;
+    const uint16_t* ia = st_idx + (size_t)(2 * r) * ldh;
+    const uint16_t* ib = st_idx + (size_t)(2 * r + 1) * ldh;
+    const float* va = st_vals + (size_t)(2 * r) * ldh;
+    const float* vb = st_vals + (size_t)(2 * r + 1) * ldh;
+    for (int i = tid; i < a; i += kMergeBlock) sv[i] = va[i];
+    for (int i = tid; i < b; i += kMergeBlock) sv[a + i] = vb[i];
+    __syncthreads();
+    const float* A = sv;
+    const float* B = sv + a;
+    const int d0 = tid * per < m ? tid * per : m;
+    const int d1 = d0 + per < m ? d0 + per : m;
+    // merge path: the number of A entries among the first d0 outputs (A[i] goes before B[j]
+    // when A[i] >= B[j])
+    int lo = d0 > b ? d0 - b : 0, hi = d0 < a ? d0 : a;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (A[mid] >= B[d0 - 1 - mid]) lo = mid + 1;
+      else hi = mid;
+    }
+    int i = lo, j = d0 - lo;
+    uint16_t* orow = idx + (size_t)v * ldi;
+    float* ovals = vals ? vals + (size_t)v * ldi : nullptr;
+    for (int d = d0; d < d1; ++d) {
+      const bool take_a = i < a && (j >= b || A[i] >= B[j]);
+      const float x = take_a ? A[i] : B[j];
+      orow[d] = take_a ? ia[i] : ib[j];
+      if (ovals) ovals[d] = x;
+      i += take_a ? 1 : 0;
+      j += take_a ? 0 : 1;
+    }
+    for (int d = m + tid; d < m_al; d += kMergeBlock) {
+      orow[d] = 0xffff;
+      if (ovals) ovals[d] = -INFINITY;
+    }
+    __syncthreads();                         // sv is reused by the next row
   }
 }
 
@@ -224,20 +321,21 @@ __global__ __launch_bounds__(BLOCK) void batch_sort_kernel(const BatchJob* __res
     const int i = find_unit(prefix, nlist, u);
     J = &jobs[list[i]];
     v = u - prefix[i];
-    load_row<BLOCK, EPT>(J->W, J->n, v, raw);
+    load_row<BLOCK, EPT>(J->W, J->n, Run{v, 0, J->n - 1}, raw);
   }
   for (; u < total; u += gridDim.x) {
     const BatchJob* Jc = J;
     const int vc = v;
-    row_keys<BLOCK, EPT>(raw, Jc->n, vc, key, idp);
+    row_keys<BLOCK, EPT>(raw, Run{vc, 0, Jc->n - 1}, key, idp);
     const int u2 = u + (int)gridDim.x;
     if (u2 < total) {
       const int i = find_unit(prefix, nlist, u2);
       J = &jobs[list[i]];
       v = u2 - prefix[i];
-      load_row<BLOCK, EPT>(J->W, J->n, v, raw);
+      load_row<BLOCK, EPT>(J->W, J->n, Run{v, 0, J->n - 1}, raw);
     }
-    sort_row_keys<BLOCK, EPT>(key, idp, Jc->n, vc, Jc->idx, Jc->vals, Jc->ldi, smem);
+    sort_row_keys<BLOCK, EPT>(key, idp, Jc->n - 1, Jc->idx + (size_t)vc * Jc->ldi,
+                              Jc->vals ? Jc->vals + (size_t)vc * Jc->ldi : nullptr, smem);
   }
 }
 
@@ -313,6 +411,14 @@ hipError_t sort_init_attributes() {
   if ((e = sort_attr_t<b, t>(i)) != hipSuccess) return e;
   TMFG_SORT_CFGS(X)
 #undef X
+  const void* ks[2] = {(const void*)sort_halves_kernel<kHalfBlock, kHalfEpt>, (const void*)merge_halves_kernel};
+  for (const void* k : ks) {
+    hipFuncAttributes a;
+    if ((e = hipFuncGetAttributes(&a, k)) != hipSuccess) return e;
+    if ((e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)(kLdsBytes - a.sharedSizeBytes))) != hipSuccess)
+      return e;
+  }
   return hipSuccess;
 }
 
@@ -345,7 +451,40 @@ hipError_t launch_batch_sort(const BatchJob* jobs, const int* list, const int* p
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, hipStream_t s) {
+// Staging of the two-run sort: two runs per row, each with this stride.
+int64_t sort_stage_stride(int n) { return round_up((n + 1) / 2, 8); }
+size_t sort_stage_bytes(int n) {
+  if (n - 1 <= kMaxLdsSortN) return 0;
+  const int rows = n < kStageRows ? n : kStageRows;
+  return (size_t)rows * 2 * (size_t)sort_stage_stride(n) * (sizeof(uint16_t) + sizeof(float));
+}
+
+hipError_t launch_sort_rows(const float* W, int n, uint16_t* idx, float* vals, int64_t ldi, void* stage,
+                            hipStream_t s) {
+  if (n - 1 > kMaxLdsSortN) {
+    if (!stage) return hipErrorInvalidValue;
+    const int h = n / 2;
+    const int64_t ldh = sort_stage_stride(n);
+    const int rows_max = n < kStageRows ? n : kStageRows;
+    uint16_t* st_idx = (uint16_t*)stage;
+    float* st_vals = (float*)((uint8_t*)stage + (size_t)rows_max * 2 * ldh * sizeof(uint16_t));
+    const size_t half_lds = RowSort<kHalfBlock, kHalfEpt>::lds_bytes();
+    const size_t merge_lds = (size_t)(n - 1) * sizeof(float);
+    const int cus = g_cus > 0 ? g_cus : 256;
+    for (int v0 = 0; v0 < n; v0 += rows_max) {
+      const int rows = n - v0 < rows_max ? n - v0 : rows_max;
+      const int g1 = 2 * rows < cus ? 2 * rows : cus;
+      hipLaunchKernelGGL((sort_halves_kernel<kHalfBlock, kHalfEpt>), dim3(g1), dim3(kHalfBlock), half_lds, s, W, n,
+                         h, v0, rows, st_idx, st_vals, ldh);
+      hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      const int g2 = rows < cus ? rows : cus;
+      hipLaunchKernelGGL(merge_halves_kernel, dim3(g2), dim3(kMergeBlock), merge_lds, s, st_idx, st_vals, ldh, n, h,
+                         v0, rows, idx, vals, ldi);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
   const int cfg = kClassDefault[sort_class(n)];
   switch (cfg) {
 #define X(i, b, t) \

@@ -39,11 +39,15 @@ def test_status_strings():
 def test_host_side_argument_errors():
     lib = binding.lib()
     h = ctypes.c_void_p()
-    assert lib.tmfg_plan_create(None, 100, 10, 0) == 1
-    assert lib.tmfg_plan_create(ctypes.byref(h), 3, 10, 0) == 2
-    assert lib.tmfg_plan_create(ctypes.byref(h), 20481, 10, 0) == 2
-    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 1, 0) == 2
-    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1 << 10) == 1
+    assert lib.tmfg_plan_create(None, 100, 10, 1, 0) == 1
+    assert lib.tmfg_plan_create(ctypes.byref(h), 3, 10, 1, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 32769, 10, 1, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 1, 1, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, -1, 0) == 2
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1, 1 << 10) == 1
+    assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1, binding.IDX32) == 1     # declared, not provided
+    # corr-tmfg keeps a 16-bit vertex per face in LDS: up to n = 20480
+    assert lib.tmfg_plan_create(ctypes.byref(h), 20481, 10, 1, binding.rule_corr_prefix(4)) == 2
     # face-rule flags: corr-tmfg needs a prefix in [1, 16], and excludes the paper's heap rule
     # (a well-formed job with placeholder pointers: a bad rule is rejected before any HIP call,
     # a good one gets as far as the HIP runtime, which has no device here)
@@ -54,7 +58,7 @@ def test_host_side_argument_errors():
     pj = ctypes.cast(jobs, ctypes.c_void_p)
     for bad in (binding.RULE_CORR, binding.rule_corr_prefix(17), binding.rule_corr_prefix(255),
                 binding.rule_corr_prefix(2) | binding.RULE_PAPER, 3 << binding.PREFIX_SHIFT):
-        assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, bad) == 1, hex(bad)
+        assert lib.tmfg_plan_create(ctypes.byref(h), 100, 10, 1, bad) == 1, hex(bad)
         assert lib.tmfg_batch_create(ctypes.byref(h), pj, 1, bad) == 1, hex(bad)
     import torch
     if torch.cuda.device_count() == 0:       # with a device this would build a real batch
@@ -171,7 +175,8 @@ def test_batch_footprint_host_side():
         arr = (binding.Job * len(jobs))(*jobs)
         return lib.tmfg_batch_footprint_bytes(ctypes.cast(arr, ctypes.c_void_p), len(jobs), 0)
 
-    assert fp(job(3)) == 0 and fp(job(20481)) == 0          # n outside [4, 20480]
+    assert fp(job(3)) == 0 and fp(job(20481)) == 0          # n outside [4, 20480] (batches)
+    assert fp(job(20480)) > 0
     assert fp(job(100, steps=False)) == 0                   # steps needed from n = 5
     assert fp(job(4, steps=False)) > 0
     neither = job(100)
