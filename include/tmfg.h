@@ -233,10 +233,14 @@ tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count
    host footprint (staged input, results) fit in what is free. Whenever one of n_streams
    stream slots is idle, admitted requests (up to max_batch, grouped by size class unless
    TMFG_SERVER_FIFO) are dispatched there as one grouped batch (the kernels of
-   tmfg_batch_run, launched directly), so a new batch starts while earlier ones still run. A request's results stay in the pinned region
-   until it is polled: requests that are never polled hold host memory and can stall
-   admission. Every request gets the result tmfg_build gives it, bit for bit.
-   submit, poll and stats may be called from any host thread. */
+   tmfg_batch_run, launched directly), so a new batch starts while earlier ones still run.
+   A request completes on its own, as soon as its build has finished, not with its batch:
+   the device publishes each build's status as it ends, the scheduler copies those words
+   every 0.25 ms and then the finished requests' results, and frees their device memory at
+   once. A request's results stay in the pinned region until it is polled: requests that
+   are never polled hold host memory and can stall admission. Every request gets the result
+   tmfg_build gives it, bit for bit. submit, poll and stats may be called from any host
+   thread. */
 typedef struct tmfg_server_s* tmfg_server;
 
 typedef struct {
@@ -270,7 +274,7 @@ typedef struct {
   int32_t status;         /* out: tmfg_status of the build */
   int64_t arrival_ns;     /* out: server clock (tmfg_server_now_ns) */
   int64_t dispatch_ns;    /* out: when its batch was enqueued */
-  int64_t done_ns;        /* out: when the scheduler saw its batch finish */
+  int64_t done_ns;        /* out: when its results were in pinned memory */
 } tmfg_server_result;
 
 typedef struct {

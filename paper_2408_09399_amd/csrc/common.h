@@ -19,6 +19,18 @@ constexpr int kMaxBatchN = 20480;
 constexpr int kLdsBytes = 160 * 1024;   // LDS of one gfx950 workgroup
 constexpr int kMinN = 4;
 
+// Host copies of one build's outputs (pinned, coherent host memory), which the loop fills
+// and publishes when the build ends, for a reader outside the launch (servers). order null:
+// none.
+struct HostOut {
+  int32_t* order;
+  int32_t* edges;
+  int32_t* steps;
+  float* step_gain;
+  int32_t* faces;
+  int32_t* status;         // written last, with a system-scope release
+};
+
 // Error flags raised on the device; the loop kernel turns them into a tmfg_status.
 enum : uint32_t {
   kFlagNonFinite = 1u << 0,

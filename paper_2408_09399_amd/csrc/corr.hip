@@ -108,9 +108,9 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
     if (hdr && tid == 0) hdr->live = 0;
     const uint32_t fl = *P.flags;
     if (fl) {
-      if (tid == 0) {
-        *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
-      }
+      const int32_t st = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+      if (tid == 0) *P.status = st;
+      if (P.hout.order) publish_outputs(P.hout, P.order, P.edges, P.steps, P.step_gain, P.faces, n, st);
       return;
     }
   }
@@ -505,6 +505,8 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
       P.stats[24] = s_compactions;
     }
   }
+  if (P.hout.order)
+    publish_outputs(P.hout, P.order, P.edges, P.steps, P.step_gain, P.faces, n, s_stop ? 8 : 0);
 }
 
 __global__ __launch_bounds__(cBlock) void tmfg_corr_kernel(LoopParams P) {
@@ -548,9 +550,11 @@ __global__ __launch_bounds__(cBlock) void batch_corr_kernel(const BatchJob* __re
     P.resume = 0;
     P.state = nullptr;
     P.max_rounds = kWalkRounds;
+    P.hout = J.hout;
     run_corr(P, smem);
     __syncthreads();
   }
+
 }
 
 size_t corr_lds_bytes(int n) { return corr_layout(n).total; }

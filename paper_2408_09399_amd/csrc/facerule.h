@@ -266,6 +266,30 @@ __device__ __forceinline__ uint64_t paper_face(const float* W, const uint16_t* i
   return group_max_u64<G>(k);
 }
 
+// Copies a finished build's outputs (n vertices; none but the status when st is not TMFG_OK)
+// to the host copies in h, then stores the status there with a system-scope release, so a
+// host thread that reads the status while the launch still runs finds the outputs complete.
+// The whole workgroup calls it, after its last output store.
+__device__ __forceinline__ void publish_outputs(const HostOut& h, const int32_t* order, const int32_t* edges,
+                                                const int32_t* steps, const float* step_gain, const int32_t* faces,
+                                                int n, int32_t st) {
+  // every wave's output stores are complete and visible across the device before any is read
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (st == 0) {
+    const int nt = (int)blockDim.x, t = (int)threadIdx.x;
+    for (int i = t; i < n; i += nt) h.order[i] = order[i];
+    for (int i = t; i < 2 * (3 * n - 6); i += nt) h.edges[i] = edges[i];
+    for (int i = t; i < 4 * (n - 4); i += nt) h.steps[i] = steps[i];
+    for (int i = t; i < n - 4; i += nt) h.step_gain[i] = step_gain[i];
+    for (int i = t; i < 3 * (2 * n - 4); i += nt) h.faces[i] = faces[i];
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");            // system scope
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(h.status, st, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __device__ __forceinline__ uint64_t rec_key(const uint4& r) { return ((uint64_t)r.x << 32) | r.y; }
 __device__ __forceinline__ int rec_face(const uint4& r) { return 0xffff - (int)(r.y >> 16); }
 __device__ __forceinline__ int rec_vertex(const uint4& r) { return (int)(r.y & 0xffffu); }

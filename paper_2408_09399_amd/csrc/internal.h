@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "common.h"
+
 namespace tmfg {
 
 // Pearson similarity (standardise + FP32-MFMA GEMM).
@@ -56,6 +58,7 @@ struct LoopParams {
   int resume;              // continue from the saved state (the rows were compacted since)
   uint8_t* state;          // saved state, loop_state_bytes(n) bytes; null: no compaction
   int max_rounds;          // walk rounds before a walk gives up and its face is swept (exact either way)
+  HostOut hout;            // optional (servers): host copies of the outputs, published at the end
 };
 constexpr int kWalkRounds = 64;   // the round limit of single builds and of untuned batches
 constexpr int kMaxPrefix = 16;   // largest corr-tmfg prefix size
@@ -108,6 +111,7 @@ struct BatchJob {
   float* step_gain;
   int32_t* faces;
   int32_t* status;
+  HostOut hout;            // optional (servers): host copies of the outputs, published at the end
 };
 
 // Grouped launches over the instances of a batch. Each takes a device list of job indices

@@ -535,9 +535,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // Errors raised by the kernels that produced W stop the build here.
     const uint32_t fl = *P.flags;
     if (fl) {
-      if (tid == 0) {
-        *P.status = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
-      }
+      const int32_t st = (fl & kFlagNonFinite) ? 3 : (fl & kFlagAsymmetric) ? 4 : (fl & kFlagDegenerate) ? 5 : 8;
+      if (tid == 0) *P.status = st;
+      if (P.hout.order) publish_outputs(P.hout, P.order, P.edges, P.steps, P.step_gain, P.faces, n, st);
       return;
     }
   }
@@ -1010,6 +1010,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       for (int i = 25; i < 32; ++i) P.stats[i] = 0;
     }
   }
+  if (P.hout.order)
+    publish_outputs(P.hout, P.order, P.edges, P.steps, P.step_gain, P.faces, n, s_stop ? 8 : 0);
 }
 
 template <bool Paper, int CI>
@@ -1057,6 +1059,7 @@ __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __re
     P.resume = 0;
     P.state = nullptr;
     P.max_rounds = max_rounds;
+    P.hout = J.hout;
     run_loop<Paper, kItersSmall>(P, smem);
     __syncthreads();
   }

@@ -7,12 +7,17 @@
 // creation, so serving never calls the HIP allocator. Whenever a stream slot is idle, the
 // head request and the waiting requests of its size class (all waiting requests with
 // TMFG_SERVER_FIFO), up to max_batch, go there as one batch: the grouped kernels of the
-// batched form, launched directly, then one copy of each request's results to pinned
-// memory and an event. A request completes with its batch, so grouping by size keeps small
-// builds from waiting for the long serial chains of large ones. The scheduler polls the slots' events; a finished request frees its
-// device range and its staged input at once, and its pinned results when the caller
-// collects them. Several slots let a new batch start while the long serial chains of an
-// earlier one still run.
+// batched form, launched directly, and an event. Several slots let a new batch start while
+// the long serial chains of an earlier one still run.
+//
+// A request completes on its own, not with its batch: the loop workgroup that finishes an
+// instance copies its outputs into the request's range of the pinned region (allocated
+// coherent, so device writes reach host memory) and then stores its status there with a
+// system-scope release. The scheduler reads the open requests' status words (atomic
+// acquire loads, once per pass of its loop, which always sleeps between passes) and
+// finishes each request whose build has ended: its results are already in pinned memory.
+// A finished request frees its device range and its staged input at once, and its pinned
+// results when the caller collects them.
 #include "../../include/tmfg.h"
 #include "arena.h"
 #include "batchplan.h"
@@ -88,7 +93,7 @@ struct Request {
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t done = nullptr;
+  hipEvent_t done = nullptr;         // the batch's kernels have finished
   char* d_desc = nullptr;            // device: descriptors, lists, queue counter
   char* h_desc = nullptr;            // pinned staging of descriptors and lists
   std::vector<Request*> reqs;
@@ -161,6 +166,17 @@ hipError_t dispatch(tmfg_server s, Slot& slot) {
   for (int i = 0; i < count; ++i) {
     Request* r = slot.reqs[i];
     tmfg::batch_job_desc(jobs[i], s->dev_base + r->dev_off + r->x_bytes + ResultLayout(r->n).bytes, hj[i]);
+    // the host copies the loop fills at the end of the build; the status word is read by the
+    // scheduler, so it holds TMFG_PENDING before any kernel of the batch is enqueued
+    const ResultLayout rl(r->n);
+    char* h = s->host_base + r->hr_off;
+    hj[i].hout.order = (int32_t*)(h + rl.order);
+    hj[i].hout.edges = (int32_t*)(h + rl.edges);
+    hj[i].hout.steps = (int32_t*)(h + rl.steps);
+    hj[i].hout.step_gain = (float*)(h + rl.gain);
+    hj[i].hout.faces = (int32_t*)(h + rl.faces);
+    hj[i].hout.status = (int32_t*)(h + rl.status);
+    __atomic_store_n(hj[i].hout.status, (int32_t)TMFG_PENDING, __ATOMIC_RELEASE);
   }
   std::memcpy(hi, spec.ints.data(), spec.ints.size() * 4);
   tmfg::BatchLaunch L;
@@ -179,36 +195,46 @@ hipError_t dispatch(tmfg_server s, Slot& slot) {
                             hipMemcpyHostToDevice, st)) != hipSuccess)
       return e;
   if ((e = tmfg::batch_enqueue(spec, L, st)) != hipSuccess) return e;
-  for (Request* r : slot.reqs)
-    if ((e = hipMemcpyAsync(s->host_base + r->hr_off, s->dev_base + r->dev_off + r->x_bytes, r->res_bytes,
-                            hipMemcpyDeviceToHost, st)) != hipSuccess)
-      return e;
   return hipEventRecord(slot.done, st);
 }
 
-// Marks a slot's requests finished (lock held).
-void finish(tmfg_server s, Slot& slot, int32_t forced_status) {
-  const int64_t t = clock_ns();
-  for (Request* r : slot.reqs) {
-    if (forced_status != TMFG_OK) {
-      r->status = forced_status;
-    } else {
-      int32_t st;
-      std::memcpy(&st, s->host_base + r->hr_off + ResultLayout(r->n).status, 4);
-      r->status = st;
-    }
-    r->done = t;
-    r->state = State::Done;
-    s->dev_alloc.release(r->dev_off, r->dev_bytes);
-    s->host_alloc.release(r->hx_off, r->x_bytes);
-    s->lat_ms.push_back((double)(t - r->arrival) * 1e-6);
-    s->min_arrival = std::min(s->min_arrival, r->arrival);
-    ++s->completed;
-  }
-  s->last_done = t;
-  slot.reqs.clear();
-  slot.busy = false;
+// The published status of request r (pinned memory the device writes), or TMFG_PENDING.
+int32_t published(tmfg_server s, const Request* r) {
+  return __atomic_load_n((const int32_t*)(s->host_base + r->hr_off + ResultLayout(r->n).status), __ATOMIC_ACQUIRE);
+}
+
+// Marks one request finished (lock held): frees its device range and staged input.
+void finish_request(tmfg_server s, Request* r, int32_t status, int64_t t) {
+  r->status = status;
+  r->done = t;
+  r->state = State::Done;
+  s->dev_alloc.release(r->dev_off, r->dev_bytes);
+  s->host_alloc.release(r->hx_off, r->x_bytes);
+  s->lat_ms.push_back((double)(t - r->arrival) * 1e-6);
+  s->min_arrival = std::min(s->min_arrival, r->arrival);
+  s->last_done = std::max(s->last_done, t);
+  ++s->completed;
   s->cv_done.notify_all();
+}
+
+// Finishes the slot's requests whose builds have published their results and takes them off
+// the slot (lock held): a finished request may be collected, and freed, by tmfg_server_poll as
+// soon as the lock is released. Once the batch's kernels have ended (`all`), every request
+// left is finished, one whose status was not published with `forced_status`, and the slot is
+// free again.
+void sweep_slot(tmfg_server s, Slot& slot, bool all, int32_t forced_status) {
+  const int64_t t = clock_ns();
+  for (auto it = slot.reqs.begin(); it != slot.reqs.end();) {
+    Request* r = *it;
+    const int32_t st = published(s, r);
+    if (st != TMFG_PENDING || all) {
+      finish_request(s, r, st != TMFG_PENDING ? st : forced_status, t);
+      it = slot.reqs.erase(it);
+    } else {
+      ++it;
+    }
+  }
+  if (all) slot.busy = false;
 }
 
 void scheduler(tmfg_server s) {
@@ -222,12 +248,14 @@ void scheduler(tmfg_server s) {
       if (!slot.busy) continue;
       const hipError_t q = hipEventQuery(slot.done);
       if (q == hipSuccess) {
-        finish(s, slot, TMFG_OK);
+        sweep_slot(s, slot, true, TMFG_E_INTERNAL);   // every build of a finished batch publishes
       } else if (q == hipErrorNotReady) {
         busy = true;
+        sweep_slot(s, slot, false, TMFG_OK);
       } else {
         tmfg::record_hip_error((int)q);
-        finish(s, slot, TMFG_E_HIP);
+        hipStreamSynchronize(slot.stream);
+        sweep_slot(s, slot, true, TMFG_E_HIP);
       }
     }
     if (s->stop && !busy) break;
@@ -274,7 +302,7 @@ void scheduler(tmfg_server s) {
       if (e != hipSuccess) {
         tmfg::record_hip_error((int)e);
         hipStreamSynchronize(slot.stream);
-        finish(s, slot, TMFG_E_HIP);
+        sweep_slot(s, slot, true, TMFG_E_HIP);
       } else {
         busy = true;
       }
@@ -327,7 +355,8 @@ tmfg_status tmfg_server_create(tmfg_server* out, const tmfg_server_config* cfg) 
   s->ints_cap = tmfg::batch_ints_capacity(cfg->max_batch);
   const size_t desc_bytes = s->jobs_bytes + tmfg::align256(s->ints_cap * 4) + kAlign;
   if ((e = hipGetDevice(&s->device)) != hipSuccess || (e = hipMalloc((void**)&s->dev_base, cfg->hbm_budget)) != hipSuccess ||
-      (e = hipHostMalloc((void**)&s->host_base, cfg->host_budget, 0)) != hipSuccess) {
+      // coherent: the loops' copies of finished builds' results reach host memory as they are written
+      (e = hipHostMalloc((void**)&s->host_base, cfg->host_budget, hipHostMallocCoherent)) != hipSuccess) {
     server_free(s);
     return fail(e);
   }

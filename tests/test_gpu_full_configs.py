@@ -5,7 +5,8 @@
   bit for bit (W included), and the oracle on the largest instances.
 * Served requests of n log-uniform over 100..8000 with L = 256, some of them n >= 4096 (the
   largest size class), arriving while earlier dispatches are still on the device: every
-  result equals its own single build, and the oracle on a sample that includes n >= 4096.
+  result equals its own single build, and the oracle on a sample that includes n >= 4096;
+  requests of one dispatch complete at their own times.
 """
 import time
 
@@ -96,6 +97,13 @@ def test_c5_sized_requests_arriving_in_flight_equal_solo_and_oracle():
     overlap = any(g1["dispatch_ns"] < g2["arrival_ns"] and g2["dispatch_ns"] < g1["done_ns"]
                   for g1 in got for g2 in got)
     assert overlap
+    # requests complete on their own: within one dispatch, the shorter builds are done well
+    # before the longest one
+    by_dispatch = {}
+    for g in got:
+        by_dispatch.setdefault(g["dispatch_ns"], []).append(g["done_ns"])
+    spreads = [max(v) - min(v) for v in by_dispatch.values() if len(v) >= 2]
+    assert spreads and max(spreads) > 2_000_000, spreads
     solo = _solo_builds([to_dev(X) for X in Xs])
     for i, (X, g, s) in enumerate(zip(Xs, got, solo)):
         assert g["status"] == 0, (i, g["status"])
