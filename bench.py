@@ -28,6 +28,14 @@ import time
 
 import numpy as np
 
+# The request server runs each dispatch slot on its own stream, and each stream needs a
+# hardware queue of its own: HIP shares GPU_MAX_HW_QUEUES queues (4 unless set) among all
+# of a process's streams, torch's included, and two slots on one queue serialize. Raised
+# here, before anything in the process initialises HIP.
+SERVER_SLOTS = 8
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 2 * SERVER_SLOTS:
+    os.environ["GPU_MAX_HW_QUEUES"] = str(2 * SERVER_SLOTS)
+
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_MFMA_TFLOPS = 157.3
 
@@ -41,7 +49,7 @@ def parse():
     ap.add_argument("--batch", type=int, default=512, help="instances in the c4 batch")
     ap.add_argument("--requests", type=int, default=2200, help="c5: requests per replay (the first 200 warm up)")
     ap.add_argument("--max-batch", type=int, default=512, help="c5: requests one server dispatch groups")
-    ap.add_argument("--streams", type=int, default=4, help="c5: server dispatches in flight")
+    ap.add_argument("--streams", type=int, default=SERVER_SLOTS, help="c5: server dispatches in flight")
     ap.add_argument("--no-serial", action="store_true", help="c5: skip the serial plain-build comparison")
     ap.add_argument("--serial-requests", type=int, default=300,
                     help="c5: requests of the trace (from its start) replayed as serial plain builds")

@@ -235,19 +235,26 @@ tmfg_status tmfg_build_batch(tmfg_plan plan, const tmfg_job* jobs, int32_t count
    TMFG_SERVER_FIFO) are dispatched there as one grouped batch (the kernels of
    tmfg_batch_run, launched directly), so a new batch starts while earlier ones still run.
    A request completes on its own, as soon as its build has finished, not with its batch:
-   the device publishes each build's status as it ends, the scheduler copies those words
-   every 0.25 ms and then the finished requests' results, and frees their device memory at
-   once. A request's results stay in the pinned region until it is polled: requests that
-   are never polled hold host memory and can stall admission. Every request gets the result
-   tmfg_build gives it, bit for bit. submit, poll and stats may be called from any host
-   thread. */
+   the workgroup that finishes a build copies its outputs into the request's range of the
+   pinned region (allocated coherent) and then stores its status word there with a
+   system-scope release; the scheduler reads the open requests' status words between its
+   passes (every 20 us while work is in flight), finishes each published request and frees
+   its device memory at once. A request's results stay in the pinned region until it is
+   polled: requests that are never polled hold host memory and can stall admission. Every
+   request gets the result tmfg_build gives it, bit for bit. submit, poll and stats may be
+   called from any host thread.
+   Each stream slot should have a hardware queue of its own. HIP gives a process
+   GPU_MAX_HW_QUEUES queues (4 by default) and shares them among all of its streams, the
+   caller's included; two slots on one queue run their dispatches one after the other,
+   which raises latency under load. Keep n_streams within the queues the process's other
+   streams leave free, or raise GPU_MAX_HW_QUEUES before the process first uses HIP. */
 typedef struct tmfg_server_s* tmfg_server;
 
 typedef struct {
   size_t hbm_budget;      /* device bytes for requests in flight */
   size_t host_budget;     /* pinned host bytes for staged inputs and unread results */
   int32_t max_batch;      /* requests one dispatch groups, at most (1..4096) */
-  int32_t n_streams;      /* dispatches in flight at once (1..4) */
+  int32_t n_streams;      /* dispatches in flight at once (1..8), one stream each */
   int32_t n_max;          /* largest n accepted (4..20480) */
   int32_t L_max;          /* largest L accepted (>= 2) */
   uint32_t flags;         /* TMFG_SERVER_FIFO, a face rule (TMFG_SERVER_RULE_PAPER, or the plan

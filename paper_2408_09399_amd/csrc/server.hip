@@ -45,7 +45,7 @@ static uint32_t server_rule_flags(uint32_t flags) {
 
 namespace {
 
-constexpr int kMaxSlots = 4;
+constexpr int kMaxSlots = 8;
 constexpr int kMaxBatch = 4096;
 constexpr size_t kAlign = 256;
 

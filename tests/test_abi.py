@@ -89,7 +89,7 @@ def test_server_host_side_argument_errors():
     assert lib.tmfg_server_create(None, pc) == 1
     assert lib.tmfg_server_create(ctypes.byref(h), None) == 1
     for field, bad, code in [("hbm_budget", 0, 1), ("host_budget", 0, 1), ("max_batch", 0, 1),
-                             ("max_batch", 4097, 1), ("n_streams", 0, 1), ("n_streams", 5, 1),
+                             ("max_batch", 4097, 1), ("n_streams", 0, 1), ("n_streams", 9, 1),
                              ("n_max", 3, 2), ("n_max", 20481, 2), ("L_max", 1, 2), ("flags", 4, 1),
                              ("flags", binding.RULE_CORR, 1), ("flags", binding.rule_corr_prefix(20), 1),
                              ("flags", binding.SERVER_RULE_PAPER | binding.rule_corr_prefix(2), 1)]:
