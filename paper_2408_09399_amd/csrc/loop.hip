@@ -60,7 +60,6 @@ constexpr int kMaxSel = 48;                      // chunks loaded per selection 
 constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
 static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
 static_assert(kMaxWork <= kBlock, "one thread publishes each recomputed face");
-// 64-face chunks of the largest build, and the chunk maxima each lane of a wave covers
 // 64-face chunks of a build and the chunk maxima each lane of a wave covers: the loop is
 // compiled for two bounds, up to n = 20480 (batches and most builds) and up to kMaxN
 constexpr int chunk_iters(int n_max) { return ((2 * n_max - 4 + 63) / 64 + kWave - 1) / kWave; }
@@ -88,8 +87,8 @@ struct Work {
 // Each round scans kSpan positions of every list (kScan per lane) and takes the first kCand
 // uninserted entries at or after the list's position; the lane that holds such an entry
 // evaluates it, with the similarity to that list's corner carried by the sorted row and the
-// other two read from W. Ranks come from four ballots over the group (positions are ordered
-// by lane, then by entry). An uninserted vertex not yet evaluated sits after the list's
+// other two read from W. Ranks come from a scan of the lanes' counts over the group
+// (positions are ordered by lane, then by entry). An uninserted vertex not yet evaluated sits after the list's
 // bound entry (the next uninserted entry, or the last position scanned), so its similarity
 // to that corner is at most the bound entry's value. A list whose span holds no uninserted
 // entry is then scanned kSkipLoads * 128 positions at a time (bitmap only) until one is
@@ -179,9 +178,7 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       const int before = (int)(incl - cnt);
       seen[t] = (int)group_max_u32<kGroup>(incl);
       // the first kCand go to slots t*kCand + rank of the group's buffer; the entry of rank
-      // kCand (if any) is the list's bound entry
-      // the entry of rank kCand (if any, in one lane) is the list's bound entry: its value and
-      // position are kept
+      // kCand (if any, in one lane) is the list's bound entry: its value and position are kept
       bval[t] = 0.0f;
       bpos[t] = -1;
 #pragma unroll
