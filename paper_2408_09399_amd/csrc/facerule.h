@@ -102,6 +102,15 @@ __device__ __forceinline__ int group_min_i32(int x) {
   if (G >= 16) x = min(x, (int)dpp32<kDppMirror>((uint32_t)x));
   return x;
 }
+// The value of lane 15 of each 16-lane row, in every lane of the row (DPP row_newbcast:15,
+// which the compiler's DPP builtin does not accept for this target). The compiler does not
+// see the DPP read inside the asm, so the asm provides the two wait states a DPP read of a
+// VGPR that a VALU instruction has just written needs.
+__device__ __forceinline__ uint32_t row_last_u32(uint32_t x) {
+  uint32_t r;
+  asm("s_nop 1\n\tv_mov_b32_dpp %0, %1 row_newbcast:15 row_mask:0xf bank_mask:0xf" : "=v"(r) : "v"(x));
+  return r;
+}
 // Inclusive prefix sum inside each 16-lane row (row_shr by 1, 2, 4, 8; lanes shifted in from
 // outside the row contribute 0).
 __device__ __forceinline__ uint32_t row_scan_u32(uint32_t x) {

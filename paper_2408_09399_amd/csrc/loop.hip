@@ -67,10 +67,14 @@ constexpr int kItersSmall = chunk_iters(kMaxBatchN), kItersBig = chunk_iters(kMa
 // Time the sub-steps of one walk group (stats [16..19]); the waits it adds slow that group.
 constexpr bool kWalkDiag = false;
 
-// Per-group staging of a walk round's candidates.
+// Per-group staging of a walk round. List t's slots start at t * kSlot: slot r < kCand holds
+// the uninserted entry of rank r (id, similarity); slot kCand holds the list's bound entry,
+// the entry of rank kCand (its position in place of an id, and its similarity) or, when the
+// span held at most kCand uninserted entries, the similarity at the span's last position.
+constexpr int kSlot = kCand + 1;
 struct GroupBuf {
-  uint16_t cid[3 * kCand];
-  float cval[3 * kCand];
+  uint16_t cid[3 * kSlot];
+  float cval[3 * kSlot];
 };
 
 struct Work {
@@ -88,13 +92,17 @@ struct Work {
 // uninserted entries at or after the list's position; the lane that holds such an entry
 // evaluates it, with the similarity to that list's corner carried by the sorted row and the
 // other two read from W. Ranks come from a scan of the lanes' counts over the group
-// (positions are ordered by lane, then by entry). An uninserted vertex not yet evaluated sits after the list's
-// bound entry (the next uninserted entry, or the last position scanned), so its similarity
-// to that corner is at most the bound entry's value. A list whose span holds no uninserted
-// entry is then scanned kSkipLoads * 128 positions at a time (bitmap only) until one is
-// found. The code is written without data-dependent branches around loads, so each round
-// costs two dependent trips to memory (list entries, then candidate similarities), plus one
-// per skip scan. Returns false when it ran out of rounds.
+// (positions are ordered by lane, then by entry); the candidates and each list's bound entry
+// are staged in the group's LDS buffer by the lanes that hold them, and read back by all. An
+// uninserted vertex not yet evaluated sits after the list's bound entry (the next uninserted
+// entry, or the last position scanned), so its similarity to that corner is at most the
+// bound entry's value. Each lane keeps the best key of the candidates it evaluated; the walk
+// ends when any lane's key beats the bound, and the group's best is taken once at the end.
+// A list whose span holds no uninserted entry is then scanned kSkipLoads * 128 positions at
+// a time (bitmap only) until one is found. The code is written without data-dependent
+// branches around loads, so each round costs two dependent trips to memory (list entries,
+// then candidate similarities), plus one per skip scan. Returns false when it ran out of
+// rounds.
 __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint16_t* ptr, GroupBuf& gb, int a,
                           int b, int c, int gl, int gbase, uint64_t& best_out, int* rounds, int* gathers, int* skips,
                           unsigned long long* wt) {
@@ -141,8 +149,7 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     int id[3][kScan];
     float val[3][kScan];
     uint32_t um[3], take[3], insw[3][kScan];
-    int seen[3], bpos[3];
-    float bval[3];
+    int seen[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) {
       const uint32_t wd[2] = {iv[t].x, iv[t].y};
@@ -172,44 +179,49 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       for (int j = 0; j < kScan; ++j) um[t] |= (~(insw[t][j] >> (id[t][j] & 31)) & 1u) << j;
       um[t] &= skip[t] ? 0u : (lo & hi);
       // ranks: an inclusive scan of the lanes' counts over the group by DPP row shifts;
-      // the group total is the scan's maximum
+      // the group total is the scan's value in the group's last lane
       const uint32_t cnt = (uint32_t)__popc(um[t]);
       const uint32_t incl = row_scan_u32(cnt);
       const int before = (int)(incl - cnt);
-      seen[t] = (int)group_max_u32<kGroup>(incl);
-      // the first kCand go to slots t*kCand + rank of the group's buffer; the entry of rank
-      // kCand (if any, in one lane) is the list's bound entry: its value and position are kept
-      bval[t] = 0.0f;
-      bpos[t] = -1;
+      seen[t] = (int)row_last_u32(incl);
+      // ranks 0 .. kCand - 1 are staged as candidates; rank kCand, the bound entry, with its
+      // position in place of the id
 #pragma unroll
       for (int j = 0; j < kScan; ++j) {
         const int rank = before + __popc(um[t] & ((1u << j) - 1));
-        const bool on = (um[t] >> j) & 1u;
-        if (on && rank < kCand) {
-          gb.cid[t * kCand + rank] = (uint16_t)id[t][j];
-          gb.cval[t * kCand + rank] = val[t][j];
+        if (((um[t] >> j) & 1u) && rank <= kCand) {
+          gb.cid[t * kSlot + rank] = (uint16_t)(rank < kCand ? id[t][j] : q[t] + j);
+          gb.cval[t * kSlot + rank] = val[t][j];
         }
-        const bool isb = on && rank == kCand;
-        bval[t] = isb ? val[t][j] : bval[t];
-        bpos[t] = isb ? q[t] + j : bpos[t];
       }
+      // a span with at most kCand uninserted entries: the last position scanned bounds it
+      if (gl == kGroup - 1 && seen[t] <= kCand) gb.cval[t * kSlot + kCand] = val[t][kScan - 1];
       take[t] = seen[t] < kCand ? seen[t] : kCand;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
     TMFG_WT(0);
-    // (3) evaluate the staged candidates, two per lane: lane gl takes slot gl (list a if
-    //     gl < 8, else list b) and slot 16 + gl (list c, lanes gl < 8). The two similarities not
-    //     carried by the list are read from W, all loads issued before any is used. The
-    //     gain keeps the order ((W[a][u] + W[b][u]) + W[c][u]); for a candidate of list a or
-    //     b the first sum is the list's own value plus the other of a, b (addition commutes).
+    // (3) evaluate the staged candidates, two per lane: lane gl takes slot gl of list a
+    //     (gl < kCand) or of list b (the others), and slot gl of list c (lanes gl < kCand).
+    //     The two similarities not carried by the list are read from W, all loads issued
+    //     before any is used. The gain keeps the order ((W[a][u] + W[b][u]) + W[c][u]); for a
+    //     candidate of list a or b the first sum is the list's own value plus the other of
+    //     a, b (addition commutes).
     static_assert(kCand == 8 && kGroup == 16 && kSlots == 2, "the slot layout below");
     const bool second = gl >= kCand;                  // slot gl holds a list-b candidate
     const bool ok0 = (gl & (kCand - 1)) < (int)(second ? take[1] : take[0]);
     const bool ok1 = !second && gl < (int)take[2];
-    const int slc1 = second ? 3 * kCand - 1 : 2 * kCand + gl;   // a slot inside the buffer
-    const int cu0 = (int)gb.cid[gl], cu1 = (int)gb.cid[slc1];
-    const float cv0 = gb.cval[gl], cv1 = gb.cval[slc1];
+    const int slc0 = gl + (second ? kSlot - kCand : 0);
+    const int slc1 = second ? 3 * kSlot - 1 : 2 * kSlot + gl;   // a slot inside the buffer
+    const int cu0 = (int)gb.cid[slc0], cu1 = (int)gb.cid[slc1];
+    const float cv0 = gb.cval[slc0], cv1 = gb.cval[slc1];
+    float bv[3];
+    int bp[3];
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      bv[t] = gb.cval[t * kSlot + kCand];
+      bp[t] = (int)gb.cid[t * kSlot + kCand];
+    }
     const int u0 = ok0 ? cu0 : 0, u1 = ok1 ? cu1 : 0;
     const float wo0 = (second ? Wx[0] : Wx[1])[u0];   // the other of a, b
     const float wc0 = Wx[2][u0];
@@ -218,12 +230,12 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
     const uint64_t k1 = cand_key((wa1 + wb1) + cv1, u1);
     uint64_t k = ok0 ? k0 : 0;
     k = (ok1 && k1 > k) ? k1 : k;
+    best = k > best ? k : best;
     ng += (ok0 ? 2 : 0) + (ok1 ? 2 : 0);
     TMFG_WT(1);
-    // (4) bounds, next positions, cached starts. Values move between the group's lanes by
-    //     DPP reductions inside the row, each with one contributing lane or the group
-    //     minimum; everything is computed for every list and then selected, so the whole
-    //     row stays active. A list being skipped this round keeps its state.
+    // (4) bounds, next positions, cached starts, all uniform over the group. The span's first
+    //     uninserted position is needed only until the list's cached start is settled. A list
+    //     being skipped this round keeps its state.
     float bound[3];
     bool exhausted = false, skipping = false;
 #pragma unroll
@@ -231,28 +243,23 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
       const bool live = !skip[t];
       const int end = (pos[t] & ~(kScan - 1)) + kSpan;
       const bool big = seen[t] > kCand;
-      // the span's first uninserted position, if any (positions grow with the lane)
-      const int first = group_min_i32(um[t] ? q[t] + (int)__builtin_ctz(um[t]) : 0x7fffffff);
-      // bound entry: the first entry not evaluated (one lane holds it) when more than kCand
-      // were seen, else the last position scanned (the group's last lane)
-      const bool mine = big ? bpos[t] >= 0 : gl == kGroup - 1;
-      const uint32_t kv = mine ? ord_f32(big ? bval[t] : val[t][kScan - 1]) : 0u;
-      const uint32_t pv = (big && bpos[t] >= 0) ? (uint32_t)bpos[t] : 0u;
-      const uint32_t kb = group_max_u32<kGroup>(kv);
-      const int pb = (int)group_max_u32<kGroup>(pv);
+      if (!tight[t]) {
+        // positions grow with the lane
+        const int first = group_min_i32(um[t] ? q[t] + (int)__builtin_ctz(um[t]) : 0x7fffffff);
+        newp[t] = live ? (first != 0x7fffffff ? first : min(end, m)) : newp[t];
+        tight[t] = live && first != 0x7fffffff;
+      }
       skipping |= !live;
-      if (!tight[t]) newp[t] = live ? (first != 0x7fffffff ? first : min(end, m)) : newp[t];
-      tight[t] = tight[t] || (live && first != 0x7fffffff);
-      bound[t] = (live && (big || end < m)) ? unord_f32(kb) : -INFINITY;
+      bound[t] = (live && (big || end < m)) ? bv[t] : -INFINITY;
       exhausted |= live && !big && end >= m;         // the list is used up: nothing unseen
-      pos[t] = live ? (big ? pb : min(end, m)) : pos[t];
+      pos[t] = live ? (big ? bp[t] : min(end, m)) : pos[t];
       skip[t] = !live || (!big && end < m && seen[t] == 0);   // a fully inserted stretch: scan ahead wide
     }
-    k = group_max_u64(k);
-    best = k > best ? k : best;
     const float T = (bound[0] + bound[1]) + bound[2];
     // A list being skipped has no bound this round; only exhaustion can end the walk then.
-    done = exhausted || (!skipping && best != 0 && (uint32_t)(best >> 32) > ord_f32(T));
+    // The group's best beats T exactly when some lane's does.
+    const uint64_t beat = __builtin_amdgcn_ballot_w64((uint32_t)(best >> 32) > ord_f32(T));
+    done = exhausted || (!skipping && ((beat >> gbase) & 0xffffu) != 0);
     TMFG_WT(2);
     // (5) wide scans, one list at a time, for lists in a fully inserted stretch
     if (!done && (skip[0] || skip[1] || skip[2])) {
@@ -299,7 +306,7 @@ __device__ bool walk_face(const LoopParams& P, int m, const uint32_t* bits, uint
 #undef TMFG_WT
   *rounds += r;
   *gathers += ng;
-  best_out = best;
+  best_out = group_max_u64(best);
   return done;
 }
 
