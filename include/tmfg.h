@@ -214,9 +214,24 @@ tmfg_status tmfg_batch_destroy(tmfg_batch batch);
    [0..7] sort configuration index of each size class (-1: class absent), [8] rows per sort
    workgroup (0: one resident fill of the device), [9] persistent loop workgroups,
    [10] configurations timed, [11] milliseconds spent tuning, [12] walk rounds before a
-   face is swept instead (64 untuned; 64, 16 or 8 tuned), [13..15] reserved. The
-   configuration never changes results. */
+   face is swept instead (64 untuned; 64, 16 or 8 tuned), [13] rows of the correlation
+   GEMM's tile for instances with n < 1024 and [14] for the others (128 or 64; 0: no such
+   instance, or no instance given as series), [15] 1 when the configuration came from the
+   tuning cache instead of timing. The configuration never changes results.
+   The tuner keeps its choices for the process and, when the environment variable
+   TMFG_TUNE_CACHE names a writable file, in that file across processes, keyed by the
+   device architecture and compute units, the HIP runtime version, the face rule and
+   validation flags, and the batch's shape (instances per (log2 n, log2 L) bucket, counts
+   rounded to a power of two); a later batch of the same key takes the stored choice. */
 tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]);
+
+/* Apply a launch configuration in the layout of tmfg_batch_config ([10], [11], [15] are
+   not read; entries of absent size classes and GEMM groups are not looked at). Each sort
+   configuration must suit its class, [8] >= 0, 1 <= [9] <= the workgroups the device holds
+   at once, 1 <= [12] <= 64, [13] and [14] 128 or 64. Waits for the device, then re-captures
+   the batch's graph. TMFG_E_INVALID, with nothing changed, when a value is out of range.
+   Results do not depend on the configuration. */
+tmfg_status tmfg_batch_set_config(tmfg_batch batch, const int32_t cfg[16]);
 
 /* Device bytes a batch over these jobs holds; 0 if a job is invalid. */
 size_t tmfg_batch_footprint_bytes(const tmfg_job* jobs, int32_t count, uint32_t flags);

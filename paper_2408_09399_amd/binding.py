@@ -59,6 +59,7 @@ SIGNATURES = {
     "tmfg_batch_destroy": (_I, [_P]),
     "tmfg_batch_footprint_bytes": (ctypes.c_size_t, [_P, _I, ctypes.c_uint32]),
     "tmfg_batch_config": (_I, [_P, ctypes.POINTER(_I)]),
+    "tmfg_batch_set_config": (_I, [_P, ctypes.POINTER(_I)]),
     "tmfg_build_batch": (_I, [_P, _P, _I, _P]),
     "tmfg_server_create": (_I, [ctypes.POINTER(_P), _P]),
     "tmfg_server_submit": (_I, [_P, _P, _I, _I, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64)]),
@@ -398,7 +399,19 @@ class Batch:
         _check(_lib().tmfg_batch_config(self._h, out), "tmfg_batch_config")
         v = list(out)
         return {"sort_config": v[0:8], "sort_rows_per_wg": v[8], "loop_workgroups": v[9],
-                "tune_trials": v[10], "tune_ms": v[11], "walk_rounds": v[12]}
+                "tune_trials": v[10], "tune_ms": v[11], "walk_rounds": v[12],
+                "gemm_tile": v[13:15], "from_cache": bool(v[15])}
+
+    def set_config(self, cfg: dict) -> None:
+        """Apply a launch configuration given as config() returns it (tmfg_batch_set_config);
+        raises on a value out of range."""
+        v = [0] * 16
+        v[0:8] = cfg["sort_config"]
+        v[8] = cfg["sort_rows_per_wg"]
+        v[9] = cfg["loop_workgroups"]
+        v[12] = cfg["walk_rounds"]
+        v[13:15] = cfg["gemm_tile"]
+        _check(_lib().tmfg_batch_set_config(self._h, (_I * 16)(*v)), "tmfg_batch_set_config")
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:

@@ -13,10 +13,14 @@
 #include "batchplan.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
+#include <string>
 #include <vector>
 
 namespace tmfg {
@@ -68,7 +72,7 @@ tmfg_status job_scratch_bytes(const tmfg_job& j, size_t* bytes) {
   return TMFG_OK;
 }
 
-size_t batch_ints_capacity(int count) { return (size_t)10 * count + 12 + 24 * 64; }
+size_t batch_ints_capacity(int count) { return (size_t)12 * count + 16 + 30 * 64; }
 
 tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, BatchSpec& spec) {
   spec = BatchSpec();
@@ -79,7 +83,10 @@ tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, Batc
     const tmfg_status st = job_scratch_bytes(jobs[i], &spec.scratch[i]);
     if (st != TMFG_OK) return st;
   }
-  std::vector<int> lx, lw, la(count), pre_rows{0}, pre_tiles{0}, pre_vt{0}, pre_cols{0};
+  std::vector<int> lx, lw, la(count), pre_rows{0}, pre_vt{0}, pre_cols{0};
+  std::vector<int> lg[kGemmGroups], pre_tiles[kGemmGroups][2];
+  for (int g = 0; g < kGemmGroups; ++g)
+    for (int t = 0; t < 2; ++t) pre_tiles[g][t].push_back(0);
   std::vector<int> lsort[8], pre_sort[8];
   int nmax_sort[8] = {0};
   for (int c = 0; c < 8; ++c) pre_sort[c].push_back(0);
@@ -90,7 +97,9 @@ tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, Batc
     if (j.X) {
       lx.push_back(i);
       pre_rows.push_back(pre_rows.back() + (int)round_up(j.n, corr_row_pad()));
-      pre_tiles.push_back(pre_tiles.back() + corr_tiles(j.n));
+      const int g = j.n < kGemmSplitN ? 0 : 1;
+      lg[g].push_back(i);
+      for (int t = 0; t < 2; ++t) pre_tiles[g][t].push_back(pre_tiles[g][t].back() + corr_tiles(j.n, kGemmTiles[t]));
     } else if (!(flags & TMFG_NO_VALIDATE)) {
       lw.push_back(i);
       pre_vt.push_back(pre_vt.back() + validate_tiles(j.n));
@@ -122,7 +131,8 @@ tmfg_status batch_describe(const tmfg_job* jobs, int count, uint32_t flags, Batc
     return g;
   };
   spec.stdz = list(lx, pre_rows, 0);
-  spec.gemm = list(lx, pre_tiles, 0);
+  for (int g = 0; g < kGemmGroups; ++g)
+    for (int t = 0; t < 2; ++t) spec.gemm[g][t] = list(lg[g], pre_tiles[g][t], 0);
   spec.valid = list(lw, pre_vt, 0);
   spec.seed = list(la, pre_cols, 0);
   for (int c = 0; c < 8; ++c) spec.sort[c] = list(lsort[c], pre_sort[c], nmax_sort[c]);
@@ -173,9 +183,8 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
   if ((e = launch_batch_standardize(L.d_jobs, lp(spec.stdz), pp(spec.stdz), spec.stdz.nlist, spec.stdz.total, s)) !=
       hipSuccess)
     return e;
-  if ((e = launch_batch_gemm(L.d_jobs, lp(spec.gemm), pp(spec.gemm), spec.gemm.nlist, spec.gemm.total, s)) !=
-      hipSuccess)
-    return e;
+  for (int g = 0; g < kGemmGroups; ++g)
+    if ((e = batch_enqueue_gemm(spec, L, g, s)) != hipSuccess) return e;
   if ((e = launch_batch_validate(L.d_jobs, lp(spec.valid), pp(spec.valid), spec.valid.nlist, spec.valid.total, s)) !=
       hipSuccess)
     return e;
@@ -192,6 +201,13 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
     return launch_batch_corr(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.prefix, s);
   return launch_batch_loop(L.d_jobs, I + spec.o_order, spec.count, L.d_queue, L.grid, spec.n_max, spec.paper,
                            L.max_rounds, s);
+}
+
+hipError_t batch_enqueue_gemm(const BatchSpec& spec, const BatchLaunch& L, int group, hipStream_t s) {
+  const GroupList& g = spec.gemm[group][L.gemm_tile[group]];
+  if (g.nlist == 0) return hipSuccess;
+  return launch_batch_gemm(L.d_jobs, L.d_ints + g.o_list, L.d_ints + g.o_prefix, g.nlist, g.total,
+                           kGemmTiles[L.gemm_tile[group]], s);
 }
 
 hipError_t batch_enqueue_sort(const BatchSpec& spec, const BatchLaunch& L, int cls, hipStream_t s) {
@@ -239,6 +255,8 @@ struct tmfg_batch_s {
   std::vector<tmfg_job> jobs;   // the job set this batch was made for
   int tune_trials = 0;          // autotuning: configurations timed, and milliseconds spent
   float tune_ms = 0.0f;
+  bool tune_cached = false;     // the tuned configuration came from the tuning cache
+  int max_grid = 1;             // loop workgroups the device holds at once
 };
 
 namespace {
@@ -275,9 +293,150 @@ hipError_t time_best(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, F e
   return hipSuccess;
 }
 
+// The launch configuration as tmfg_batch_config reports it ([10], [11], [15] aside).
+void config_out(tmfg_batch b, int32_t out[16]) {
+  for (int i = 0; i < 16; ++i) out[i] = 0;
+  for (int c = 0; c < tmfg::kSortClasses; ++c) {
+    const int cfg = b->launch.sort_cfg[c];
+    out[c] = b->spec.sort[c].nlist == 0 ? -1 : (cfg >= 0 ? cfg : tmfg::sort_default_config(c));
+  }
+  out[8] = b->launch.sort_rows;
+  out[9] = b->launch.grid;
+  out[12] = b->launch.max_rounds;
+  for (int g = 0; g < tmfg::kGemmGroups; ++g)
+    out[13 + g] = b->spec.gemm[g][0].nlist == 0 ? 0 : tmfg::kGemmTiles[b->launch.gemm_tile[g]];
+}
+
+// Checks a configuration against the batch (entries of absent sort classes and GEMM groups
+// are not looked at) and, when valid, applies it to the launch description.
+bool config_apply(tmfg_batch b, const int32_t cfg[16], int max_grid) {
+  tmfg::BatchLaunch L = b->launch;
+  for (int c = 0; c < tmfg::kSortClasses; ++c) {
+    if (b->spec.sort[c].nlist == 0) continue;
+    if (cfg[c] < 0 || cfg[c] >= tmfg::kSortConfigs || !tmfg::sort_config_fits(cfg[c], c)) return false;
+    L.sort_cfg[c] = cfg[c];
+  }
+  if (cfg[8] < 0 || cfg[9] < 1 || cfg[9] > max_grid || cfg[12] < 1 || cfg[12] > tmfg::kWalkRounds) return false;
+  L.sort_rows = cfg[8];
+  L.grid = cfg[9];
+  L.max_rounds = cfg[12];
+  for (int g = 0; g < tmfg::kGemmGroups; ++g) {
+    if (b->spec.gemm[g][0].nlist == 0) continue;
+    if (cfg[13 + g] == tmfg::kGemmTiles[0]) L.gemm_tile[g] = 0;
+    else if (cfg[13 + g] == tmfg::kGemmTiles[1]) L.gemm_tile[g] = 1;
+    else return false;
+  }
+  b->launch = L;
+  return true;
+}
+
+// (Re)captures the batch's launches into its graph.
+hipError_t capture(tmfg_batch b) {
+  hipError_t e;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  if (!b->capture_stream && (e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess)
+    return e;
+  if ((e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) return e;
+  const hipError_t ee = tmfg::batch_enqueue(b->spec, b->launch, b->capture_stream);
+  e = hipStreamEndCapture(b->capture_stream, &b->graph);
+  if (ee != hipSuccess) return ee;
+  if (e != hipSuccess) return e;
+  return hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+}
+
+// Tuned configurations, kept for the process and, when the environment variable
+// TMFG_TUNE_CACHE names a file, across processes (one line per entry: key, tab, the 16
+// configuration words). The key holds what the choice depends on: the device architecture
+// and compute units, the HIP runtime version, the face rule and validation flags, and the
+// batch's shape as the number of instances per (log2 n, log2 L) bucket, rounded to a power
+// of two.
+std::mutex g_tune_mu;
+std::map<std::string, std::vector<int32_t>> g_tune_cache;
+bool g_tune_loaded = false;
+
+std::string tune_key(tmfg_batch b) {
+  hipDeviceProp_t prop;
+  int rt = 0;
+  if (hipGetDeviceProperties(&prop, b->device) != hipSuccess || hipRuntimeGetVersion(&rt) != hipSuccess) return "";
+  std::map<std::pair<int, int>, int> hist;
+  for (const tmfg_job& j : b->jobs) {
+    const int nb = 31 - __builtin_clz((unsigned)j.n);
+    const int lb = j.X ? 31 - __builtin_clz((unsigned)std::max(j.L, 1)) : -1;
+    ++hist[{nb, lb}];
+  }
+  std::string k = "tmfg-tune-1 ";
+  k += prop.gcnArchName;
+  k += " cu" + std::to_string(prop.multiProcessorCount) + " hip" + std::to_string(rt);
+  k += " f" + std::to_string(b->flags & (TMFG_NO_VALIDATE | tmfg::kRuleFlags)) + " ";
+  for (const auto& h : hist) {
+    const int q = 32 - __builtin_clz((unsigned)h.second);   // count rounded to a power of two
+    k += std::to_string(h.first.first) + "." + std::to_string(h.first.second) + ":" + std::to_string(q) + ",";
+  }
+  return k;
+}
+
+void tune_cache_load() {
+  if (g_tune_loaded) return;
+  g_tune_loaded = true;
+  const char* path = std::getenv("TMFG_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  std::string line;
+  for (int ch; (ch = std::fgetc(f)) != EOF;) {
+    if (ch != '\n') {
+      line.push_back((char)ch);
+      continue;
+    }
+    const size_t tab = line.find('\t');
+    if (tab != std::string::npos) {
+      std::vector<int32_t> v;
+      const char* p = line.c_str() + tab + 1;
+      char* q = nullptr;
+      for (int i = 0; i < 16; ++i, p = q) {
+        const long x = std::strtol(p, &q, 10);
+        if (q == p) break;
+        v.push_back((int32_t)x);
+      }
+      if (v.size() == 16) g_tune_cache[line.substr(0, tab)] = v;
+    }
+    line.clear();
+  }
+  std::fclose(f);
+}
+
+bool tune_cache_get(const std::string& key, int32_t cfg[16]) {
+  if (key.empty()) return false;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache_load();
+  const auto it = g_tune_cache.find(key);
+  if (it == g_tune_cache.end()) return false;
+  std::copy(it->second.begin(), it->second.end(), cfg);
+  return true;
+}
+
+void tune_cache_put(const std::string& key, const int32_t cfg[16]) {
+  if (key.empty()) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  tune_cache_load();
+  g_tune_cache[key] = std::vector<int32_t>(cfg, cfg + 16);
+  const char* path = std::getenv("TMFG_TUNE_CACHE");
+  if (!path || !*path) return;
+  if (FILE* f = std::fopen(path, "a")) {
+    std::fprintf(f, "%s\t", key.c_str());
+    for (int i = 0; i < 16; ++i) std::fprintf(f, i ? " %d" : "%d", (int)cfg[i]);
+    std::fprintf(f, "\n");
+    std::fclose(f);
+  }
+}
+
 // Autotuning on the batch's own inputs: one full run puts every phase's inputs in place,
 // then each knob is timed on the phase it affects, one knob at a time, keeping a change only
 // when it is at least 2% faster:
+//   * the correlation GEMM's tile (128 or 64 rows) for instances below 1024 and for the rest;
 //   * the launch configuration (threads x slots per thread) of each size class's row sort;
 //   * the rows each sort workgroup takes (resident fill of the device, or 2, 4, 16 rows);
 //   * the number of persistent loop workgroups (all that fit, three quarters, half);
@@ -304,6 +463,17 @@ hipError_t autotune(tmfg_batch b) {
       return hipSuccess;
     };
     float best = 0.0f, t = 0.0f;
+    for (int g = 0; g < tmfg::kGemmGroups; ++g) {
+      if (S.gemm[g][0].nlist == 0) continue;
+      L.gemm_tile[g] = 0;
+      auto one = [&]() { return tmfg::batch_enqueue_gemm(S, L, g, st); };
+      if ((e = time_best(st, e0, e1, 2, one, &best)) != hipSuccess) goto done;
+      ++b->tune_trials;
+      L.gemm_tile[g] = 1;
+      if ((e = time_best(st, e0, e1, 2, one, &t)) != hipSuccess) goto done;
+      ++b->tune_trials;
+      if (!(t < 0.98f * best)) L.gemm_tile[g] = 0;
+    }
     for (int c = 0; c < tmfg::kSortClasses; ++c) {
       if (S.sort[c].nlist == 0) continue;
       L.sort_cfg[c] = tmfg::sort_default_config(c);
@@ -437,27 +607,25 @@ tmfg_status tmfg_batch_create(tmfg_batch* out, const tmfg_job* jobs, int32_t cou
     return fail(e);
   }
 
-  if ((flags & TMFG_BATCH_AUTOTUNE) && (e = autotune(b)) != hipSuccess) {
-    batch_free(b);
-    return fail(e);
+  b->max_grid = L.grid;
+  if (flags & TMFG_BATCH_AUTOTUNE) {
+    const std::string key = tune_key(b);
+    int32_t cfg[16];
+    if (tune_cache_get(key, cfg) && config_apply(b, cfg, b->max_grid)) {
+      b->tune_cached = true;
+    } else {
+      if ((e = autotune(b)) != hipSuccess) {
+        batch_free(b);
+        return fail(e);
+      }
+      config_out(b, cfg);
+      tune_cache_put(key, cfg);
+    }
   }
 
-  if (!(flags & TMFG_BATCH_NO_GRAPH)) {
-    if ((e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-      batch_free(b);
-      return fail(e);
-    }
-    const hipError_t ee = tmfg::batch_enqueue(b->spec, L, b->capture_stream);
-    e = hipStreamEndCapture(b->capture_stream, &b->graph);
-    if (ee != hipSuccess || e != hipSuccess) {
-      batch_free(b);
-      return fail(ee != hipSuccess ? ee : e);
-    }
-    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess) {
-      batch_free(b);
-      return fail(e);
-    }
+  if (!(flags & TMFG_BATCH_NO_GRAPH) && (e = capture(b)) != hipSuccess) {
+    batch_free(b);
+    return fail(e);
   }
   *out = b;
   return TMFG_OK;
@@ -480,16 +648,23 @@ tmfg_status tmfg_batch_destroy(tmfg_batch batch) {
 
 tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]) {
   if (!batch || !out) return TMFG_E_INVALID;
-  for (int i = 0; i < 16; ++i) out[i] = 0;
-  for (int c = 0; c < tmfg::kSortClasses; ++c) {
-    const int cfg = batch->launch.sort_cfg[c];
-    out[c] = batch->spec.sort[c].nlist == 0 ? -1 : (cfg >= 0 ? cfg : tmfg::sort_default_config(c));
-  }
-  out[8] = batch->launch.sort_rows;
-  out[9] = batch->launch.grid;
+  config_out(batch, out);
   out[10] = batch->tune_trials;
   out[11] = (int32_t)(batch->tune_ms + 0.5f);
-  out[12] = batch->launch.max_rounds;
+  out[15] = batch->tune_cached ? 1 : 0;
+  return TMFG_OK;
+}
+
+tmfg_status tmfg_batch_set_config(tmfg_batch batch, const int32_t cfg[16]) {
+  if (!batch || !cfg) return TMFG_E_INVALID;
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return fail(e);
+  const tmfg::BatchLaunch keep = batch->launch;
+  if (!config_apply(batch, cfg, batch->max_grid)) return TMFG_E_INVALID;
+  if (batch->exec && (e = capture(batch)) != hipSuccess) {
+    batch->launch = keep;
+    return fail(e);
+  }
   return TMFG_OK;
 }
 

@@ -18,12 +18,18 @@ struct GroupList {
   size_t o_list = 0, o_prefix = 0;
 };
 
+// The correlation GEMM runs in two groups, instances below kGemmSplitN and the others, each
+// with its own tile (kGemmTiles[t]); the lists of both tiles are kept for each group.
+constexpr int kGemmGroups = 2, kGemmSplitN = 1024;
+constexpr int kGemmTiles[2] = {128, 64};
+
 struct BatchSpec {
   int count = 0, n_max = 0;
   bool paper = false;                // every instance uses the paper's face rule
   int prefix = 0;                    // > 0: every instance uses corr-tmfg with this prefix
   std::vector<int> ints;             // every list, each padded to a multiple of 64 ints
-  GroupList stdz, gemm, valid, seed, sort[8];
+  GroupList stdz, valid, seed, sort[8];
+  GroupList gemm[kGemmGroups][2];    // [group][tile index]
   size_t o_order = 0;                // job indices by n descending: the loop's queue order
   std::vector<size_t> scratch;       // device scratch bytes of each job
 };
@@ -49,6 +55,7 @@ struct BatchLaunch {
   int sort_cfg[kSortClasses] = {-1, -1, -1, -1, -1, -1, -1, -1};   // -1: the class default
   int sort_rows = 0;                                        // rows per sort workgroup (0: resident fill)
   int max_rounds = kWalkRounds;                             // walk rounds before the full-row sweep
+  int gemm_tile[kGemmGroups] = {0, 0};                      // index into kGemmTiles of each GEMM group
   std::vector<std::pair<const float*, float*>> w_copies;    // caller W -> W_out
   std::vector<size_t> w_copy_bytes;
 };
@@ -58,6 +65,8 @@ hipError_t batch_enqueue(const BatchSpec& spec, const BatchLaunch& L, hipStream_
 // The row sorts of one size class alone, and the insertion loops alone (with the reset of
 // the status flags and the queue they need); inputs of each must already be in place.
 hipError_t batch_enqueue_sort(const BatchSpec& spec, const BatchLaunch& L, int cls, hipStream_t s);
+// The correlation GEMM of one group alone (its standardised inputs must be in place).
+hipError_t batch_enqueue_gemm(const BatchSpec& spec, const BatchLaunch& L, int group, hipStream_t s);
 hipError_t batch_enqueue_loop(const BatchSpec& spec, const BatchLaunch& L, hipStream_t s);
 
 // Persistent loop grid for `count` jobs of largest size n_max: the loop workgroups that

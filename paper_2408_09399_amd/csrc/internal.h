@@ -120,8 +120,9 @@ struct BatchJob {
 hipError_t launch_batch_reset(BatchJob* jobs, int count, int* queue_head, bool clear_flags, hipStream_t s);
 hipError_t launch_batch_standardize(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
                                     hipStream_t s);
+// tile: 128 (four waves per tile) or 64 (one wave per tile); W's bits do not depend on it.
 hipError_t launch_batch_gemm(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
-                             hipStream_t s);
+                             int tile, hipStream_t s);
 hipError_t launch_batch_validate(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
                                  hipStream_t s);
 hipError_t launch_batch_seed(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
@@ -142,7 +143,7 @@ hipError_t launch_batch_loop(const BatchJob* jobs, const int* order, int count, 
                              int n_max, bool paper, int max_rounds, hipStream_t s);
 hipError_t launch_batch_corr(const BatchJob* jobs, const int* order, int count, int* queue_head, int grid,
                              int n_max, int prefix, hipStream_t s);
-int corr_tiles(int n);                        // upper-triangular correlation tiles of n rows
+int corr_tiles(int n, int tile = 128);        // upper-triangular correlation tiles of n rows
 hipError_t sort_init_attributes();            // LDS limits of the kernels (set once)
 hipError_t loop_init_attributes();
 hipError_t corr_init_attributes();

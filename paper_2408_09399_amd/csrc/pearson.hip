@@ -67,39 +67,50 @@ __global__ __launch_bounds__(256) void standardize_kernel(const float* __restric
 // ---------------------------------------------------------------------------------------
 // W = Z Z^T with v_mfma_f32_32x32x2_f32.
 //
-// Workgroup tile 128x128 (4 waves, each 64x64 = 2x2 MFMA blocks of 32x32), K staged
-// through LDS 32 columns at a time. Only tiles with block-row <= block-column are
-// computed; each is written to W[i][j] and mirrored to W[j][i], so W is bitwise
-// symmetric. In a diagonal tile only entries with i < j are used (their mirrors fill
-// j < i) and the diagonal is written as exactly 1.0f. Every entry is clamped to [-1, 1]
-// and -0.0 is stored as +0.0.
+// Workgroup tile TB x TB: TB = 128 (4 waves) or TB = 64 (1 wave). Every wave computes a
+// 64x64 block as 2x2 MFMA blocks of 32x32, with K staged through LDS 32 columns at a time.
+// Only tiles with block-row <= block-column are computed; each is written to W[i][j] and
+// mirrored to W[j][i], so W is bitwise symmetric. In a diagonal tile only entries with i < j
+// are used (their mirrors fill j < i) and the diagonal is written as exactly 1.0f. Every
+// entry is clamped to [-1, 1] and -0.0 is stored as +0.0.
 //
-// Summation order is a property of this kernel alone: the K dimension is walked in steps
-// of 4, each step issuing two MFMAs over the k pairs (k, k+2) and (k+1, k+3). Tile sizes
-// never change that order, so W's bits do not depend on the launch shape.
+// Summation order is a property of the wave's code alone: the K dimension is walked in
+// steps of 4, each step issuing two MFMAs over the k pairs (k, k+2) and (k+1, k+3). The tile
+// size only decides how many waves share a tile, so W's bits depend on neither the tile nor
+// the launch shape.
 //
 // Operand layout for the 32x32x2 MFMA: lane l supplies A[l % 32][l / 32] and
 // B[l / 32][l % 32]; the 16 accumulators of lane l hold D[8 (r / 4) + 4 (l / 32) + r % 4]
 // [l % 32] for r = 0..15.
 // ---------------------------------------------------------------------------------------
 namespace {
-constexpr int BM = 128, BK = 32, LDA = BK + 2;  // LDS row stride in floats (pad for banks)
-constexpr int LDT = BM + 1;
-constexpr int kGemmSmem = BM * LDT;              // floats
+constexpr int BK = 32, LDA = BK + 2;  // LDS row stride in floats (pad for banks)
 typedef float f16x __attribute__((ext_vector_type(16)));
+template <int TB>
+struct GemmShape {
+  static_assert(TB == 64 || TB == 128, "a tile is one wave's 64x64 block or 2x2 of them");
+  static constexpr int kWavesPerDim = TB / 64;
+  static constexpr int kThreads = kWavesPerDim * kWavesPerDim * kWave;
+  static constexpr int kLdt = TB + 1;                                    // output staging stride
+  static constexpr int kLoads = TB * (BK / 4) / kThreads;                // float4 per thread and operand
+  static constexpr int kSmem = TB * kLdt > 2 * TB * LDA ? TB * kLdt : 2 * TB * LDA;   // floats
+};
 }  // namespace
 
 __device__ __forceinline__ float fix_corr(float v) { return fminf(fmaxf(v, -1.0f), 1.0f) + 0.0f; }
 
+template <int TB>
 __device__ void gemm_tile(const float* __restrict__ Z, int n, int L_pad, float* __restrict__ W, int bi, int bj,
                           float* smem) {
-  const int i0 = bi * BM, j0 = bj * BM;
+  typedef GemmShape<TB> G;
+  constexpr int NT = G::kThreads, LDT = G::kLdt;
+  const int i0 = bi * TB, j0 = bj * TB;
   float* As = smem;
-  float* Bs = smem + BM * LDA;
+  float* Bs = smem + TB * LDA;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / G::kWavesPerDim, wn = wave % G::kWavesPerDim;
   const int li = lane & 31, lh = lane >> 5;
 
   f16x acc[2][2];
@@ -113,18 +124,18 @@ __device__ void gemm_tile(const float* __restrict__ Z, int n, int L_pad, float* 
   const float* Za = Z + (size_t)i0 * L_pad;
   const float* Zb = Z + (size_t)j0 * L_pad;
   for (int k0 = 0; k0 < L_pad; k0 += BK) {
-    float4 ra[4], rb[4];
+    float4 ra[G::kLoads], rb[G::kLoads];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int flat = r * 256 + tid;
+    for (int r = 0; r < G::kLoads; ++r) {
+      const int flat = r * NT + tid;
       const int row = flat >> 3, c4 = (flat & 7) * 4;
       ra[r] = *(const float4*)(Za + (size_t)row * L_pad + k0 + c4);
       rb[r] = *(const float4*)(Zb + (size_t)row * L_pad + k0 + c4);
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int flat = r * 256 + tid;
+    for (int r = 0; r < G::kLoads; ++r) {
+      const int flat = r * NT + tid;
       const int row = flat >> 3, c4 = (flat & 7) * 4;
       float2* pa = (float2*)(As + row * LDA + c4);
       float2* pb = (float2*)(Bs + row * LDA + c4);
@@ -151,7 +162,7 @@ __device__ void gemm_tile(const float* __restrict__ Z, int n, int L_pad, float* 
     }
   }
   __syncthreads();
-  // Stage the 128x128 tile in LDS so both the direct and the mirrored stores coalesce.
+  // Stage the tile in LDS so both the direct and the mirrored stores coalesce.
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -164,8 +175,8 @@ __device__ void gemm_tile(const float* __restrict__ Z, int n, int L_pad, float* 
       }
   __syncthreads();
   const bool diag = (bi == bj);
-  for (int flat = tid; flat < BM * BM; flat += 256) {
-    const int r = flat >> 7, c = flat & 127;
+  for (int flat = tid; flat < TB * TB; flat += NT) {
+    const int r = flat / TB, c = flat % TB;
     const int gi = i0 + r, gj = j0 + c;
     if (gi < n && gj < n) {
       if (!diag || r < c) W[(size_t)gi * n + gj] = fix_corr(smem[r * LDT + c]);
@@ -187,8 +198,8 @@ __global__ __launch_bounds__(256, 2) void corr_gemm_kernel(const float* __restri
   if (t >= tiles) return;
   int bi, bj;
   upper_tri_coords(t, nb, bi, bj);
-  __shared__ __attribute__((aligned(16))) float smem[kGemmSmem];
-  gemm_tile(Z, n, L_pad, W, bi, bj, smem);
+  __shared__ __attribute__((aligned(16))) float smem[GemmShape<128>::kSmem];
+  gemm_tile<128>(Z, n, L_pad, W, bi, bj, smem);
 }
 
 // Batched forms: one launch over every instance's rows / tiles.
@@ -203,20 +214,21 @@ __global__ __launch_bounds__(256) void batch_standardize_kernel(const BatchJob* 
   standardize_row(J.X, J.n, J.L, J.Z, J.L_pad, J.flags, unit - prefix[i], threadIdx.x & 63);
 }
 
-__global__ __launch_bounds__(256, 2) void batch_gemm_kernel(const BatchJob* __restrict__ jobs,
-                                                            const int* __restrict__ list,
-                                                            const int* __restrict__ prefix, int nlist,
-                                                            int total, int per_xcd) {
+template <int TB>
+__global__ __launch_bounds__(GemmShape<TB>::kThreads) void batch_gemm_kernel(const BatchJob* __restrict__ jobs,
+                                                                            const int* __restrict__ list,
+                                                                            const int* __restrict__ prefix, int nlist,
+                                                                            int total, int per_xcd) {
   const int xcd = blockIdx.x & 7;
   const int t = xcd * per_xcd + (blockIdx.x >> 3);
   if (t >= total) return;
   const int i = find_unit(prefix, nlist, t);
   const BatchJob& J = jobs[list[i]];
-  const int nb = (J.n + BM - 1) / BM;
+  const int nb = (J.n + TB - 1) / TB;
   int bi, bj;
   upper_tri_coords(t - prefix[i], nb, bi, bj);
-  __shared__ __attribute__((aligned(16))) float smem[kGemmSmem];
-  gemm_tile(J.Z, J.n, J.L_pad, J.Wdst, bi, bj, smem);
+  __shared__ __attribute__((aligned(16))) float smem[GemmShape<TB>::kSmem];
+  gemm_tile<TB>(J.Z, J.n, J.L_pad, J.Wdst, bi, bj, smem);
 }
 
 hipError_t launch_standardize(const float* X, int n, int L, float* Z, int n_pad, int L_pad, uint32_t* flags,
@@ -227,7 +239,7 @@ hipError_t launch_standardize(const float* X, int n, int L, float* Z, int n_pad,
 }
 
 hipError_t launch_corr_gemm(const float* Z, int n, int L_pad, float* W, hipStream_t s) {
-  const int nb = (n + BM - 1) / BM;
+  const int nb = (n + 127) / 128;
   const int tiles = nb * (nb + 1) / 2;
   const int per_xcd = (tiles + 7) / 8;
   hipLaunchKernelGGL(corr_gemm_kernel, dim3(8 * per_xcd), dim3(256), 0, s, Z, n, L_pad, nb, tiles, per_xcd, W);
@@ -243,19 +255,25 @@ hipError_t launch_batch_standardize(const BatchJob* jobs, const int* list, const
 }
 
 hipError_t launch_batch_gemm(const BatchJob* jobs, const int* list, const int* prefix, int nlist, int total,
-                             hipStream_t s) {
+                             int tile, hipStream_t s) {
   if (total <= 0) return hipSuccess;
   const int per_xcd = (total + 7) / 8;
-  hipLaunchKernelGGL(batch_gemm_kernel, dim3(8 * per_xcd), dim3(256), 0, s, jobs, list, prefix, nlist, total,
-                     per_xcd);
+  if (tile == 64)
+    hipLaunchKernelGGL(batch_gemm_kernel<64>, dim3(8 * per_xcd), dim3(GemmShape<64>::kThreads), 0, s, jobs, list,
+                       prefix, nlist, total, per_xcd);
+  else if (tile == 128)
+    hipLaunchKernelGGL(batch_gemm_kernel<128>, dim3(8 * per_xcd), dim3(GemmShape<128>::kThreads), 0, s, jobs, list,
+                       prefix, nlist, total, per_xcd);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-int corr_tiles(int n) {
-  const int nb = (n + BM - 1) / BM;
+int corr_tiles(int n, int tile) {
+  const int nb = (n + tile - 1) / tile;
   return nb * (nb + 1) / 2;
 }
-int corr_row_pad() { return BM; }
+int corr_row_pad() { return 128; }
 int corr_k_pad() { return BK; }
 
 }  // namespace tmfg

@@ -111,7 +111,8 @@ def test_autotuned_batch_same_results():
     torch.cuda.synchronize()
     tuned = tm.Batch(dev, flags=tm.BATCH_AUTOTUNE)
     cfg = tuned.config()
-    assert cfg["tune_trials"] > 0 and cfg["loop_workgroups"] >= 1
+    assert (cfg["tune_trials"] > 0 or cfg["from_cache"]) and cfg["loop_workgroups"] >= 1
+    assert all(t in (64, 128) for t in cfg["gemm_tile"])
     assert any(c >= 0 for c in cfg["sort_config"])
     assert cfg["walk_rounds"] in (64, 16, 8)
     for rep in range(2):
@@ -124,3 +125,124 @@ def test_autotuned_batch_same_results():
     assert base["tune_trials"] == 0 and base["walk_rounds"] == 64
     ref.close()
     tuned.close()
+
+
+def _series_inputs(ns, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, n in enumerate(ns):
+        L = int(rng.integers(30, 400))
+        k = int(rng.integers(1, min(n, 8) + 1))
+        out.append(("X", synth.planted_clusters(n, L, synth.dirichlet_sizes(rng, n, k), (0.3, 1.0),
+                                                seed=seed * 100 + i).X))
+    return out
+
+
+def test_gemm_tiles_give_the_same_bits():
+    """The correlation GEMM's tile (128 rows and four waves, or 64 rows and one wave) only
+    decides how many waves share a tile: W, and so every output, is the same bits under
+    every choice, for instances below and above the 1024 split, and equals the single
+    build's (which always uses 128)."""
+    inputs = _series_inputs([5, 64, 65, 130, 700, 1023, 1024, 1300, 2100], 31)
+    dev = [(k, to_dev(a)) for k, a in inputs]
+    b = tm.Batch(dev, keep_w=True)
+    base = b.config()
+    assert base["gemm_tile"] == [128, 128] and not base["from_cache"]
+    want = [r.to_numpy() for r in b.run()]
+    torch.cuda.synchronize()
+    for tiles in ([64, 64], [64, 128], [128, 64]):
+        cfg = dict(base, gemm_tile=tiles)
+        b.set_config(cfg)
+        assert b.config()["gemm_tile"] == tiles
+        for r in b.results:                      # stale outputs must not pass for new ones
+            r.W.fill_(float("nan"))
+        got = [r.to_numpy() for r in b.run()]
+        torch.cuda.synchronize()
+        for (kind, arr), g, w in zip(inputs, got, want):
+            assert g["status"] == 0
+            assert np.array_equal(g["W"].view(np.uint32), w["W"].view(np.uint32)), (tiles, arr.shape)
+            same_tmfg(g, w)
+    for (kind, arr), w in zip(inputs, want):
+        solo = _solo(kind, arr)
+        assert np.array_equal(solo["W"].view(np.uint32), w["W"].view(np.uint32))
+    b.close()
+
+
+def test_set_config_rejects_out_of_range_values():
+    inputs = _series_inputs([40, 300, 1500], 32)
+    b = tm.Batch([(k, to_dev(a)) for k, a in inputs])
+    base = b.config()
+    bad = [dict(base, gemm_tile=[96, 128]), dict(base, walk_rounds=0), dict(base, walk_rounds=65),
+           dict(base, loop_workgroups=0), dict(base, loop_workgroups=base["loop_workgroups"] + 1),
+           dict(base, sort_rows_per_wg=-1),
+           dict(base, sort_config=[99 if c >= 0 else c for c in base["sort_config"]])]
+    for cfg in bad:
+        with pytest.raises(RuntimeError):
+            b.set_config(cfg)
+        assert b.config() == base
+    ok = dict(base, walk_rounds=8, loop_workgroups=1, sort_rows_per_wg=4)
+    b.set_config(ok)
+    got = b.config()
+    assert (got["walk_rounds"], got["loop_workgroups"], got["sort_rows_per_wg"]) == (8, 1, 4)
+    res = [r.to_numpy() for r in b.run()]
+    torch.cuda.synchronize()
+    for (kind, arr), g in zip(inputs, res):
+        same_tmfg(g, _solo(kind, arr))
+    b.close()
+
+
+def test_tuning_cache_in_process():
+    """A second autotuned batch of the same shape takes the first one's choice from the
+    process's tuning cache, without timing, and gives the same results."""
+    inputs = _series_inputs([37, 210, 1200, 1900, 77], 33)
+    dev = [(k, to_dev(a)) for k, a in inputs]
+    first = tm.Batch(dev, flags=tm.BATCH_AUTOTUNE)
+    c1 = first.config()
+    want = [r.to_numpy() for r in first.run()]
+    torch.cuda.synchronize()
+    second = tm.Batch(dev, flags=tm.BATCH_AUTOTUNE)
+    c2 = second.config()
+    assert c2["from_cache"] and c2["tune_trials"] == 0
+    for k in ("sort_config", "sort_rows_per_wg", "loop_workgroups", "walk_rounds", "gemm_tile"):
+        assert c2[k] == c1[k], k
+    got = [r.to_numpy() for r in second.run()]
+    torch.cuda.synchronize()
+    for g, w in zip(got, want):
+        same_tmfg(g, w)
+    first.close()
+    second.close()
+
+
+_CACHE_SCRIPT = """
+import sys, json, numpy as np, torch
+sys.path.insert(0, sys.argv[1])
+import paper_2408_09399_amd as tm
+from paper_2408_09399_amd import synth
+rng = np.random.default_rng(34)
+xs = [synth.planted_clusters(n, 96, synth.dirichlet_sizes(rng, n, 3), (0.3, 1.0), seed=n).X for n in (51, 400, 1100)]
+b = tm.Batch([("X", torch.from_numpy(x).cuda()) for x in xs], flags=tm.BATCH_AUTOTUNE)
+print(json.dumps(b.config()))
+b.close()
+"""
+
+
+def test_tuning_cache_file_across_processes(tmp_path):
+    """With TMFG_TUNE_CACHE set, a later process takes the tuned choice from the file."""
+    import json
+    import os
+    import subprocess
+    import sys
+    repo = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, TMFG_TUNE_CACHE=str(tmp_path / "tune.txt"))
+    runs = []
+    for _ in range(2):
+        r = subprocess.run([sys.executable, "-c", _CACHE_SCRIPT, repo], env=env, capture_output=True, text=True,
+                           timeout=240)
+        assert r.returncode == 0, r.stderr[-2000:]
+        runs.append(json.loads(r.stdout.strip().splitlines()[-1]))
+    assert not runs[0]["from_cache"] and runs[0]["tune_trials"] > 0
+    assert runs[1]["from_cache"] and runs[1]["tune_trials"] == 0
+    for k in ("sort_config", "sort_rows_per_wg", "loop_workgroups", "walk_rounds", "gemm_tile"):
+        assert runs[1][k] == runs[0][k], k
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) == 1 and "\t" in lines[0]
