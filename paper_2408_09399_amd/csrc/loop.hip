@@ -502,6 +502,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ uint4 s_crec[kMaxSel][kWave];       // the loaded chunk records
   __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
+  __shared__ int s_b0;                           // waves done with their share of phase B0
   __shared__ int s_u4[4];                        // the vertex the last selection inserted, and the
                                                  // corners of the face it split
   __shared__ int s_adv;                          // selection's word to the advancing waves: 0 not yet,
@@ -577,6 +578,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_nsweep = 0;
       s_bmax = 0;
       s_next = 0;
+      s_b0 = 0;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -604,6 +606,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_nsweep = 0;
       s_bmax = 0;
       s_next = 0;
+      s_b0 = 0;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -655,66 +658,97 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // paper rule: stale records at or below the largest record of the chunks left unloaded
     // cannot be committed this phase, so they are not recomputed
     const uint64_t cut = Paper ? max64(floor, s_rest) : floor;
-    // all of this wave's records are requested before any is used (one trip to memory)
-    uint4 crecs[kSelPerWave];
+    if (wave < nsel) {
+      // all of this wave's records are requested before any is used (one trip to memory)
+      uint4 crecs[kSelPerWave];
 #pragma unroll
-    for (int i = 0; i < kSelPerWave; ++i) {
-      const int sl = wave + i * kWaves;
-      const int f = (sl < nsel ? sel[sl] : 0) * 64 + lane;
-      crecs[i] = P.frec[f < nf ? f : nf - 1];
-    }
+      for (int i = 0; i < kSelPerWave; ++i) {
+        const int sl = wave + i * kWaves;
+        const int f = (sl < nsel ? sel[sl] : 0) * 64 + lane;
+        crecs[i] = P.frec[f < nf ? f : nf - 1];
+      }
 #pragma unroll
-    for (int i = 0; i < kSelPerWave; ++i) {
-      const int sl = wave + i * kWaves;
-      if (sl >= nsel) break;
-      const int f = sel[sl] * 64 + lane;
-      const uint4 crec = f < nf ? crecs[i] : make_uint4(0, 0, 0, 0);
-      int link = -1;
-      for (int q = 0; q < nnew; ++q)
-        if (work[q].f == f) link = q;
-      uint64_t kfresh = 0;
-      if (link < 0 && s_ins < n) {
-        const uint64_t k = rec_key(crec);
-        const bool stale = is_ins(bits, rec_vertex(crec));
-        if (k != 0 && k > cut && stale) {
-          const int slot = atomicAdd(&s_nwork, 1);
-          if (slot < kMaxWork) {
-            work[slot] = Work{f, (int)(crec.z & 0xffffu), (int)(crec.z >> 16), (int)crec.w, 0, 0};
-            if (Paper) s_old[slot] = k;
-            link = slot;
-          } else if (Paper) {
-            atomicMax(&s_unloaded, (unsigned long long)k);
+      for (int i = 0; i < kSelPerWave; ++i) {
+        const int sl = wave + i * kWaves;
+        if (sl >= nsel) break;
+        const int f = sel[sl] * 64 + lane;
+        const uint4 crec = f < nf ? crecs[i] : make_uint4(0, 0, 0, 0);
+        int link = -1;
+        for (int q = 0; q < nnew; ++q)
+          if (work[q].f == f) link = q;
+        uint64_t kfresh = 0;
+        if (link < 0 && s_ins < n) {
+          const uint64_t k = rec_key(crec);
+          const bool stale = is_ins(bits, rec_vertex(crec));
+          if (k != 0 && k > cut && stale) {
+            const int slot = atomicAdd(&s_nwork, 1);
+            if (slot < kMaxWork) {
+              work[slot] = Work{f, (int)(crec.z & 0xffffu), (int)(crec.z >> 16), (int)crec.w, 0, 0};
+              if (Paper) s_old[slot] = k;
+              link = slot;
+            } else if (Paper) {
+              atomicMax(&s_unloaded, (unsigned long long)k);
+            }
           }
+          if (Paper && !stale) kfresh = k;
         }
-        if (Paper && !stale) kfresh = k;
+        if (Paper) {
+          kfresh = wave_max_dpp(kfresh);
+          if (lane == 0 && kfresh > s_best0) atomicMax(&s_best0, (unsigned long long)kfresh);
+        }
+        s_crec[sl][lane] = crec;
+        s_link[sl][lane] = (int16_t)link;
       }
-      if (Paper) {
-        kfresh = wave_max_dpp(kfresh);
-        if (lane == 0 && kfresh > s_best0) atomicMax(&s_best0, (unsigned long long)kfresh);
-      }
-      s_crec[sl][lane] = crec;
-      s_link[sl][lane] = (int16_t)link;
     }
-    __syncthreads();
-    TMFG_LAP(6);
-    const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
-    if (tid == 0) {
-      s_cnt[0] += nwork - nnew;
-      if (s_nwork > kMaxWork) s_cnt[17] += 1;
-      if (nsel >= kMaxSel) s_cnt[18] += 1;
+    // This wave's share of B0 is done. The stale work items are final once every wave has
+    // said so; the new faces' items were written by the selection, so their walks need not
+    // wait for B0 (no barrier here: the other waves' loads of chunk records overlap them).
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) {
+      const int done = __hip_atomic_fetch_add(&s_b0, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (done == kWaves - 1) {
+        const int nw = s_nwork < kMaxWork ? s_nwork : kMaxWork;
+        s_cnt[0] += nw - nnew;
+        if (s_nwork > kMaxWork) s_cnt[17] += 1;
+        if (nsel >= kMaxSel) s_cnt[18] += 1;
+        const uint64_t t1 = clock_ticks();
+        s_cnt[6] += t1 - s_t0;
+        s_t0 = t1;
+      }
     }
     const bool have_cand = s_ins < n;
-    // Phase B: best pair of every queued face, one group of kGroup lanes per face. Each wave
-    // takes the next kWave / kGroup faces from a counter when it is free, so a deep walk
-    // holds up only its own wave.
+    // Phase B: best pair of every queued face, one group of kGroup lanes per face. A wave
+    // takes the next batch of kWave / kGroup faces from a counter when it is free, so a deep
+    // walk holds up only its own wave. Batch 0 is the new faces (items [0, nnew)), taken by
+    // the first wave to get here; batch b >= 1 holds stale items nnew + (b - 1) * 4 ... and is
+    // walked once B0 is done everywhere.
     for (;;) {
-      int base = 0;
-      if (lane == 0) base = atomicAdd(&s_next, kWave / kGroup);
-      base = __builtin_amdgcn_readfirstlane(base);
-      if (base >= nwork) break;
+      int b = 0;
+      if (lane == 0) b = atomicAdd(&s_next, 1);
+      b = __builtin_amdgcn_readfirstlane(b);
+      int base = 0, limit = nnew;
+      if (b > 0) {
+        // a bounded wait: the other waves' B0 shares take one trip to memory; should it ever
+        // run out, the build stops with an internal error rather than walk unqueued items
+        int it = 0;
+        while (__hip_atomic_load(&s_b0, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < kWaves && it < (1 << 24))
+          ++it;
+        if (it >= (1 << 24)) {
+          if (lane == 0) {
+            *P.status = 8;
+            s_stop = 1;
+          }
+          break;
+        }
+        base = nnew + (b - 1) * (kWave / kGroup);
+        limit = s_nwork < kMaxWork ? s_nwork : kMaxWork;
+        if (base >= limit) break;
+      } else if (nnew == 0) {
+        continue;
+      }
       if (lane == 0) atomicAdd(&s_cnt[4], 1ull);
       const int item = base + (lane / kGroup);
-      if (item < nwork) {
+      if (item < limit) {
         Work& w = work[item];
         uint64_t best = 0;
         bool ok = true;
@@ -742,6 +776,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       }
     }
     __syncthreads();
+    const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
     if (tid == 0) {
       s_cnt[12] += s_bmax;
       s_bmax = 0;
@@ -796,6 +831,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     if (tid == 0) {
       s_nsweep = 0;
       s_next = 0;
+      s_b0 = 0;
       s_adv = 0;
       if (Paper) {
         s_best0 = 0;
