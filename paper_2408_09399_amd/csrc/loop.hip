@@ -58,6 +58,7 @@ constexpr int kSkipLoads = 4;                    // 16-byte loads per lane in a 
 constexpr int kMaxWork = 256;                    // faces recomputed per selection phase
 constexpr int kMaxSel = 48;                      // chunks loaded per selection phase
 constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
+constexpr int kSelWaves = 4;                     // waves that share the exact rule's selection
 static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
 static_assert(kMaxWork <= kBlock, "one thread publishes each recomputed face");
 // 64-face chunks of a build and the chunk maxima each lane of a wave covers: the loop is
@@ -75,6 +76,13 @@ constexpr int kSlot = kCand + 1;
 struct GroupBuf {
   uint16_t cid[3 * kSlot];
   float cval[3 * kSlot];
+};
+
+// What the selecting waves post to each other in a selection phase (exact rule).
+struct SelShare {
+  uint64_t part[2][kSelWaves][2];   // each wave's posted maxima, per exchange
+  int sync[2];                      // waves that have posted, per exchange
+  int napp;                         // stale chunks appended to sel[] after the phase's own ones
 };
 
 struct Work {
@@ -503,6 +511,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ int16_t s_link[kMaxSel][kWave];     // work item replacing each record, or -1
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
   __shared__ int s_b0;                           // waves done with their share of phase B0
+  __shared__ SelShare s_sel;                     // the exact rule's selecting waves' posts
   __shared__ int s_u4[4];                        // the vertex the last selection inserted, and the
                                                  // corners of the face it split
   __shared__ int s_adv;                          // selection's word to the advancing waves: 0 not yet,
@@ -579,6 +588,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_bmax = 0;
       s_next = 0;
       s_b0 = 0;
+      s_sel.sync[0] = 0;
+      s_sel.sync[1] = 0;
+      s_sel.napp = 0;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -607,6 +619,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_bmax = 0;
       s_next = 0;
       s_b0 = 0;
+      s_sel.sync[0] = 0;
+      s_sel.sync[1] = 0;
+      s_sel.napp = 0;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -653,7 +668,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // Phase B0: load the records of the queued chunks (one wave per chunk, one record per
     // lane). Each record is linked to the work item that will replace it: a new face, or a
     // stale record ranked above the floor, which is queued for recomputation.
-    const int nsel = s_nsel, nnew = s_nnew;
+    const int nsel = min(s_nsel + s_sel.napp, kMaxSel), nnew = s_nnew;
     const uint64_t floor = s_floor;
     // paper rule: stale records at or below the largest record of the chunks left unloaded
     // cannot be committed this phase, so they are not recomputed
@@ -833,6 +848,9 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_next = 0;
       s_b0 = 0;
       s_adv = 0;
+      s_sel.sync[0] = 0;
+      s_sel.sync[1] = 0;
+      s_sel.napp = 0;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -871,9 +889,207 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       }
       return;
     }
-    // Phase A: select (wave 0).
+    // Phase A: select. For large builds the exact rule spreads the scan of the chunk maxima
+    // over kSelWaves waves (below); otherwise, and always for the paper rule (whose choice of
+    // stale chunks is ordered), wave 0 selects alone.
     if (tid == 0) s_cnt[3] += 1;
-    if (wave == 0) {
+    // builds of more than two chunk maxima per lane share the scan; smaller ones gain less
+    // from it than the waves' exchanges cost
+    const bool multi = !Paper && LL.nchunk > 2 * kWave;
+    if (multi && wave < kSelWaves) {
+      // Each of the kSelWaves waves reads the maxima of its share of the chunks (lane + i *
+      // kWave for i in its range) and the inserted bits of their vertices, and posts its best
+      // record and best fresh record; all of them then take the same decision from the posted
+      // values. On an insertion they post again, the best fresh record once the new vertex is
+      // counted inserted (the floor), and each appends its own stale chunks ranked above the
+      // floor to sel[] through a counter. Which stale chunks are recomputed in a phase, and in
+      // which order, decides no result: every cached key is an upper bound, and only a fresh
+      // maximum is ever inserted.
+      constexpr int CIW = (CI + kSelWaves - 1) / kSelWaves;
+      const int ins = s_ins, F = s_F, since = s_since_insert;   // read before any wave changes them
+      uint32_t khi[CIW], klo[CIW];
+      uint32_t insm = 0;
+      int sl_lane = lane;
+      asm volatile("" : "+v"(sl_lane));
+      const int i0 = wave * CIW;
+#pragma unroll
+      for (int j = 0; j < CIW; ++j) {
+        const int ch = sl_lane + (i0 + j) * kWave;
+        const uint4 r = cmax[ch < LL.nchunk ? ch : 0];
+        khi[j] = ch < LL.nchunk ? r.x : 0u;
+        klo[j] = ch < LL.nchunk ? r.y : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < CIW; ++j)
+        insm |= is_ins(bits, (int)(klo[j] & 0xffffu)) ? (1u << j) : 0u;
+      uint64_t k1 = 0, kf = 0;
+#pragma unroll
+      for (int j = 0; j < CIW; ++j) {
+        const uint64_t k = ((uint64_t)khi[j] << 32) | klo[j];
+        k1 = max64(k1, k);
+        kf = ((insm >> j) & 1u) ? kf : max64(kf, k);
+      }
+      k1 = wave_max_dpp(k1);
+      kf = wave_max_dpp(kf);
+      // post, then wait (a bounded wait: the other selecting waves do the same work and wait
+      // for nothing else) and combine
+      auto exchange = [&](int step, uint64_t a, uint64_t b, uint64_t* ga, uint64_t* gb) -> bool {
+        if (lane == 0) {
+          s_sel.part[step][wave][0] = a;
+          s_sel.part[step][wave][1] = b;
+          __hip_atomic_fetch_add(&s_sel.sync[step], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        int it = 0;
+        while (__hip_atomic_load(&s_sel.sync[step], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < kSelWaves &&
+               it < (1 << 24))
+          ++it;
+        uint64_t xa = 0, xb = 0;
+#pragma unroll
+        for (int w = 0; w < kSelWaves; ++w) {
+          xa = max64(xa, s_sel.part[step][w][0]);
+          xb = max64(xb, s_sel.part[step][w][1]);
+        }
+        *ga = xa;
+        *gb = xb;
+        return it < (1 << 24);
+      };
+      uint64_t K1 = 0, KF = 0;
+      bool ok = exchange(0, k1, kf, &K1, &KF);
+      const int f1 = 0xffff - (int)((uint32_t)K1 >> 16);
+      int ns0 = 1, c1 = f1 >> 6, c2 = c1;
+      uint64_t fl = KF;                          // the floor for the stale chunks to append
+      bool append = ok;
+      if (!ok) {
+        append = false;
+      } else if (K1 != 0 && K1 == KF) {
+        // Fresh maximum: insert its vertex.
+        const int u = (int)((uint32_t)K1 & 0xffffu);
+        c2 = F >> 6;                             // F is even, so F and F + 1 share a chunk
+        ns0 = c2 != c1 ? 2 : 1;
+        if (wave == 0 && lane == 0) {
+          const uint4 r = cmax[c1];
+          const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
+          const int st = ins - 4;
+          P.order[ins] = u;
+          int32_t* e = P.edges + 2 * (6 + 3 * st);
+          e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
+          int32_t* sp = P.steps + 4 * st;
+          sp[0] = f1; sp[1] = x; sp[2] = y; sp[3] = z;
+          P.step_gain[st] = unord_f32(r.x);
+          bits[u >> 5] |= 1u << (u & 31);
+          int t0_ = u, t1_ = x, t2_ = y;
+          sort3(t0_, t1_, t2_);
+          work[0] = Work{f1, t0_, t1_, t2_, 0, 0};
+          t0_ = u; t1_ = y; t2_ = z;
+          sort3(t0_, t1_, t2_);
+          work[1] = Work{F, t0_, t1_, t2_, 0, 0};
+          t0_ = u; t1_ = x; t2_ = z;
+          sort3(t0_, t1_, t2_);
+          work[2] = Work{F + 1, t0_, t1_, t2_, 0, 0};
+          s_ins = ins + 1;
+          s_u4[0] = u;
+          s_u4[1] = x;
+          s_u4[2] = y;
+          s_u4[3] = z;
+          s_F = F + 2;
+          s_nwork = 3;
+          s_nnew = 3;
+          sel[0] = c1;
+          sel[1] = c2;
+          // u's bit and the four rows are written: the advancing waves may start
+          __hip_atomic_store(&s_adv, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        // The chunks of the three new faces are reloaded. Faces whose cached vertex was u are
+        // stale now; the chunks whose maximum is stale and ranks above the best fresh record
+        // that remains are loaded too, and every stale record in them ranked above that floor
+        // is recomputed along with the new faces.
+        if (ins + 1 < n) {
+#pragma unroll
+          for (int j = 0; j < CIW; ++j)
+            if ((klo[j] & 0xffffu) == (uint32_t)u) insm |= 1u << j;
+          uint64_t kf2 = 0;
+#pragma unroll
+          for (int j = 0; j < CIW; ++j) {
+            const uint64_t k = ((uint64_t)khi[j] << 32) | klo[j];
+            kf2 = ((insm >> j) & 1u) ? kf2 : max64(kf2, k);
+          }
+          kf2 = wave_max_dpp(kf2);
+          uint64_t unused = 0;
+          append = exchange(1, kf2, 0, &fl, &unused);
+          ok = append;
+        } else {
+          fl = ~0ull;
+          append = false;
+        }
+        if (wave == 0 && lane == 0) {
+          s_nsel = ns0;
+          s_floor = fl;
+          s_since_insert = 0;
+        }
+      } else if (K1 == 0 || since + 1 > nf + 8) {
+        append = false;
+        if (wave == 0 && lane == 0) {
+          *P.status = 8;
+          s_stop = 1;
+          s_nwork = 0;
+          s_nnew = 0;
+          s_nsel = 0;
+          __hip_atomic_store(&s_adv, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+      } else {
+        // Stale maximum: load every chunk whose maximum is stale and ranks above the best
+        // fresh record (the top one first) and recompute their stale records above it.
+        if (wave == 0 && lane == 0) {
+          s_cnt[16] += 1;
+          sel[0] = c1;
+          __hip_atomic_store(&s_adv, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          s_nsel = 1;
+          s_floor = KF;
+          s_nwork = 0;
+          s_nnew = 0;
+          s_since_insert = since + 1;
+        }
+      }
+      if (!ok && wave == 0 && lane == 0) {
+        // a wait ran out (it cannot, as each selecting wave posts without waiting for
+        // anything but the others' posts): stop the build with an internal error
+        *P.status = 8;
+        s_stop = 1;
+        s_nwork = 0;
+        s_nnew = 0;
+        s_nsel = 0;
+        __hip_atomic_store(&s_adv, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      if (append) {
+        // this wave's stale chunks above the floor, after the ns0 chunks of the phase's own
+        // list: one counter addition per wave, then each lane its slots
+        uint32_t pm = 0;
+#pragma unroll
+        for (int j = 0; j < CIW; ++j) {
+          const int ch = sl_lane + (i0 + j) * kWave;
+          const uint64_t k = ((uint64_t)khi[j] << 32) | klo[j];
+          pm |= (ch < LL.nchunk && ch != c1 && ch != c2 && k > fl && ((insm >> j) & 1u)) ? (1u << j) : 0u;
+        }
+        int cnt = 0;
+        uint64_t msk[CIW];
+#pragma unroll
+        for (int j = 0; j < CIW; ++j) {
+          msk[j] = __ballot((pm >> j) & 1u);
+          cnt += (int)__popcll(msk[j]);
+        }
+        int base = 0;
+        if (lane == 0 && cnt) base = atomicAdd(&s_sel.napp, cnt);
+        base = __builtin_amdgcn_readfirstlane(base);
+#pragma unroll
+        for (int j = 0; j < CIW; ++j) {
+          if ((pm >> j) & 1u) {
+            const int slot = ns0 + base + (int)__popcll(msk[j] & ((1ull << lane) - 1));
+            if (slot < kMaxSel) sel[slot] = sl_lane + (i0 + j) * kWave;
+          }
+          base += (int)__popcll(msk[j]);
+        }
+      }
+    } else if (!multi && wave == 0) {
       // Every chunk maximum this lane covers is read once (all loads in flight together),
       // then the inserted bits of their vertices; the top record, the best fresh one, the
       // floor after an insertion and the stale chunks to reload all come from these.
