@@ -215,7 +215,7 @@ __global__ __launch_bounds__(256) void batch_standardize_kernel(const BatchJob* 
 }
 
 template <int TB>
-__global__ __launch_bounds__(GemmShape<TB>::kThreads) void batch_gemm_kernel(const BatchJob* __restrict__ jobs,
+__global__ __launch_bounds__(GemmShape<TB>::kThreads, 2) void batch_gemm_kernel(const BatchJob* __restrict__ jobs,
                                                                             const int* __restrict__ list,
                                                                             const int* __restrict__ prefix, int nlist,
                                                                             int total, int per_xcd) {
