@@ -80,9 +80,10 @@ struct GroupBuf {
 
 // What the selecting waves post to each other in a selection phase (exact rule).
 struct SelShare {
-  uint64_t part[2][kSelWaves][2];   // each wave's posted maxima, per exchange
-  int sync[2];                      // waves that have posted, per exchange
-  int napp;                         // stale chunks appended to sel[] after the phase's own ones
+  uint64_t part[kSelWaves][3];   // each wave's best record, best fresh record, and best fresh
+                                 // record of another vertex than the best fresh one's
+  int sync;                      // waves that have posted
+  int napp;                      // stale chunks appended to sel[] after the phase's own ones
 };
 
 struct Work {
@@ -588,8 +589,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_bmax = 0;
       s_next = 0;
       s_b0 = 0;
-      s_sel.sync[0] = 0;
-      s_sel.sync[1] = 0;
+      s_sel.sync = 0;
       s_sel.napp = 0;
       if (Paper) {
         s_best0 = 0;
@@ -619,8 +619,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_bmax = 0;
       s_next = 0;
       s_b0 = 0;
-      s_sel.sync[0] = 0;
-      s_sel.sync[1] = 0;
+      s_sel.sync = 0;
       s_sel.napp = 0;
       if (Paper) {
         s_best0 = 0;
@@ -848,8 +847,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_next = 0;
       s_b0 = 0;
       s_adv = 0;
-      s_sel.sync[0] = 0;
-      s_sel.sync[1] = 0;
+      s_sel.sync = 0;
       s_sel.napp = 0;
       if (Paper) {
         s_best0 = 0;
@@ -899,12 +897,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     if (multi && wave < kSelWaves) {
       // Each of the kSelWaves waves reads the maxima of its share of the chunks (lane + i *
       // kWave for i in its range) and the inserted bits of their vertices, and posts its best
-      // record and best fresh record; all of them then take the same decision from the posted
-      // values. On an insertion they post again, the best fresh record once the new vertex is
-      // counted inserted (the floor), and each appends its own stale chunks ranked above the
-      // floor to sel[] through a counter. Which stale chunks are recomputed in a phase, and in
-      // which order, decides no result: every cached key is an upper bound, and only a fresh
-      // maximum is ever inserted.
+      // record, its best fresh record, and its best fresh record of another vertex than that
+      // one's; all of them then take the same decision from the posted values. On an
+      // insertion of u, the floor (the best fresh record once u counts as inserted) is the
+      // largest over the waves of their best fresh record, or of the other one where the best
+      // is u's. Each wave appends its own stale chunks ranked above the floor to sel[] through
+      // a counter. Which stale chunks are recomputed in a phase, and in which order, decides
+      // no result: every cached key is an upper bound, and only a fresh maximum is inserted.
       constexpr int CIW = (CI + kSelWaves - 1) / kSelWaves;
       const int ins = s_ins, F = s_F, since = s_since_insert;   // read before any wave changes them
       uint32_t khi[CIW], klo[CIW];
@@ -922,39 +921,47 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
 #pragma unroll
       for (int j = 0; j < CIW; ++j)
         insm |= is_ins(bits, (int)(klo[j] & 0xffffu)) ? (1u << j) : 0u;
-      uint64_t k1 = 0, kf = 0;
+      // k1: best record; b1: best fresh record, of vertex v1; b2: best fresh record of a
+      // vertex other than v1
+      uint64_t k1 = 0, b1 = 0, b2 = 0;
+      uint32_t v1 = 0xffffffffu;
 #pragma unroll
       for (int j = 0; j < CIW; ++j) {
         const uint64_t k = ((uint64_t)khi[j] << 32) | klo[j];
+        const uint32_t v = klo[j] & 0xffffu;
         k1 = max64(k1, k);
-        kf = ((insm >> j) & 1u) ? kf : max64(kf, k);
+        if (!((insm >> j) & 1u) && k != 0) {
+          if (k > b1) {
+            b2 = v != v1 ? b1 : b2;
+            b1 = k;
+            v1 = v;
+          } else if (v != v1) {
+            b2 = max64(b2, k);
+          }
+        }
       }
       k1 = wave_max_dpp(k1);
-      kf = wave_max_dpp(kf);
+      const uint64_t B1 = wave_max_dpp(b1);
+      const uint64_t B2 = wave_max_dpp(v1 != ((uint32_t)B1 & 0xffffu) ? b1 : b2);
       // post, then wait (a bounded wait: the other selecting waves do the same work and wait
       // for nothing else) and combine
-      auto exchange = [&](int step, uint64_t a, uint64_t b, uint64_t* ga, uint64_t* gb) -> bool {
-        if (lane == 0) {
-          s_sel.part[step][wave][0] = a;
-          s_sel.part[step][wave][1] = b;
-          __hip_atomic_fetch_add(&s_sel.sync[step], 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
-        int it = 0;
-        while (__hip_atomic_load(&s_sel.sync[step], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < kSelWaves &&
-               it < (1 << 24))
-          ++it;
-        uint64_t xa = 0, xb = 0;
-#pragma unroll
-        for (int w = 0; w < kSelWaves; ++w) {
-          xa = max64(xa, s_sel.part[step][w][0]);
-          xb = max64(xb, s_sel.part[step][w][1]);
-        }
-        *ga = xa;
-        *gb = xb;
-        return it < (1 << 24);
-      };
+      if (lane == 0) {
+        s_sel.part[wave][0] = k1;
+        s_sel.part[wave][1] = B1;
+        s_sel.part[wave][2] = B2;
+        __hip_atomic_fetch_add(&s_sel.sync, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      int it = 0;
+      while (__hip_atomic_load(&s_sel.sync, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < kSelWaves &&
+             it < (1 << 24))
+        ++it;
+      const bool ok = it < (1 << 24);
       uint64_t K1 = 0, KF = 0;
-      bool ok = exchange(0, k1, kf, &K1, &KF);
+#pragma unroll
+      for (int w = 0; w < kSelWaves; ++w) {
+        K1 = max64(K1, s_sel.part[w][0]);
+        KF = max64(KF, s_sel.part[w][1]);
+      }
       const int f1 = 0xffff - (int)((uint32_t)K1 >> 16);
       int ns0 = 1, c1 = f1 >> 6, c2 = c1;
       uint64_t fl = KF;                          // the floor for the stale chunks to append
@@ -963,41 +970,43 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         append = false;
       } else if (K1 != 0 && K1 == KF) {
         // Fresh maximum: insert its vertex.
-        const int u = (int)((uint32_t)K1 & 0xffffu);
+        const uint32_t u = (uint32_t)K1 & 0xffffu;
         c2 = F >> 6;                             // F is even, so F and F + 1 share a chunk
         ns0 = c2 != c1 ? 2 : 1;
-        if (wave == 0 && lane == 0) {
+        if (wave == 0) {
           const uint4 r = cmax[c1];
           const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
-          const int st = ins - 4;
-          P.order[ins] = u;
-          int32_t* e = P.edges + 2 * (6 + 3 * st);
-          e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
-          int32_t* sp = P.steps + 4 * st;
-          sp[0] = f1; sp[1] = x; sp[2] = y; sp[3] = z;
-          P.step_gain[st] = unord_f32(r.x);
-          bits[u >> 5] |= 1u << (u & 31);
-          int t0_ = u, t1_ = x, t2_ = y;
-          sort3(t0_, t1_, t2_);
-          work[0] = Work{f1, t0_, t1_, t2_, 0, 0};
-          t0_ = u; t1_ = y; t2_ = z;
-          sort3(t0_, t1_, t2_);
-          work[1] = Work{F, t0_, t1_, t2_, 0, 0};
-          t0_ = u; t1_ = x; t2_ = z;
-          sort3(t0_, t1_, t2_);
-          work[2] = Work{F + 1, t0_, t1_, t2_, 0, 0};
-          s_ins = ins + 1;
-          s_u4[0] = u;
-          s_u4[1] = x;
-          s_u4[2] = y;
-          s_u4[3] = z;
-          s_F = F + 2;
-          s_nwork = 3;
-          s_nnew = 3;
-          sel[0] = c1;
-          sel[1] = c2;
-          // u's bit and the four rows are written: the advancing waves may start
-          __hip_atomic_store(&s_adv, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          if (lane == 0) {
+            // first what the advancing waves need: u's bit and the four rows
+            bits[u >> 5] |= 1u << (u & 31);
+            s_u4[0] = (int)u;
+            s_u4[1] = x;
+            s_u4[2] = y;
+            s_u4[3] = z;
+            __hip_atomic_store(&s_adv, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            const int st = ins - 4;
+            P.order[ins] = (int)u;
+            int32_t* e = P.edges + 2 * (6 + 3 * st);
+            e[0] = u; e[1] = x; e[2] = u; e[3] = y; e[4] = u; e[5] = z;
+            int32_t* sp = P.steps + 4 * st;
+            sp[0] = f1; sp[1] = x; sp[2] = y; sp[3] = z;
+            P.step_gain[st] = unord_f32(r.x);
+            int t0_ = u, t1_ = x, t2_ = y;
+            sort3(t0_, t1_, t2_);
+            work[0] = Work{f1, t0_, t1_, t2_, 0, 0};
+            t0_ = u; t1_ = y; t2_ = z;
+            sort3(t0_, t1_, t2_);
+            work[1] = Work{F, t0_, t1_, t2_, 0, 0};
+            t0_ = u; t1_ = x; t2_ = z;
+            sort3(t0_, t1_, t2_);
+            work[2] = Work{F + 1, t0_, t1_, t2_, 0, 0};
+            s_ins = ins + 1;
+            s_F = F + 2;
+            s_nwork = 3;
+            s_nnew = 3;
+            sel[0] = c1;
+            sel[1] = c2;
+          }
         }
         // The chunks of the three new faces are reloaded. Faces whose cached vertex was u are
         // stale now; the chunks whose maximum is stale and ranks above the best fresh record
@@ -1006,17 +1015,13 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         if (ins + 1 < n) {
 #pragma unroll
           for (int j = 0; j < CIW; ++j)
-            if ((klo[j] & 0xffffu) == (uint32_t)u) insm |= 1u << j;
-          uint64_t kf2 = 0;
+            if ((klo[j] & 0xffffu) == u) insm |= 1u << j;
+          fl = 0;
 #pragma unroll
-          for (int j = 0; j < CIW; ++j) {
-            const uint64_t k = ((uint64_t)khi[j] << 32) | klo[j];
-            kf2 = ((insm >> j) & 1u) ? kf2 : max64(kf2, k);
+          for (int w = 0; w < kSelWaves; ++w) {
+            const uint64_t p1 = s_sel.part[w][1], p2 = s_sel.part[w][2];
+            fl = max64(fl, ((uint32_t)p1 & 0xffffu) != u ? p1 : p2);
           }
-          kf2 = wave_max_dpp(kf2);
-          uint64_t unused = 0;
-          append = exchange(1, kf2, 0, &fl, &unused);
-          ok = append;
         } else {
           fl = ~0ull;
           append = false;
@@ -1051,8 +1056,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         }
       }
       if (!ok && wave == 0 && lane == 0) {
-        // a wait ran out (it cannot, as each selecting wave posts without waiting for
-        // anything but the others' posts): stop the build with an internal error
+        // the wait ran out (it cannot, as each selecting wave posts without waiting for
+        // anything): stop the build with an internal error
         *P.status = 8;
         s_stop = 1;
         s_nwork = 0;
