@@ -229,8 +229,9 @@ tmfg_status tmfg_batch_config(tmfg_batch batch, int32_t out[16]);
    not read; entries of absent size classes and GEMM groups are not looked at). Each sort
    configuration must suit its class, [8] >= 0, 1 <= [9] <= the workgroups the device holds
    at once, 1 <= [12] <= 64, [13] and [14] 128 or 64. Waits for the device, then re-captures
-   the batch's graph. TMFG_E_INVALID, with nothing changed, when a value is out of range.
-   Results do not depend on the configuration. */
+   the batch's graph. TMFG_E_INVALID, with nothing changed, when a value is out of range;
+   TMFG_E_HIP when the capture fails, with the previous configuration kept and the batch
+   then launching its kernels directly. Results do not depend on the configuration. */
 tmfg_status tmfg_batch_set_config(tmfg_batch batch, const int32_t cfg[16]);
 
 /* Device bytes a batch over these jobs holds; 0 if a job is invalid. */

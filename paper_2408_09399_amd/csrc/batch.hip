@@ -425,10 +425,12 @@ void tune_cache_put(const std::string& key, const int32_t cfg[16]) {
   g_tune_cache[key] = std::vector<int32_t>(cfg, cfg + 16);
   const char* path = std::getenv("TMFG_TUNE_CACHE");
   if (!path || !*path) return;
+  // one write of the whole line, so that processes appending at once do not interleave
+  std::string line = key + "\t";
+  for (int i = 0; i < 16; ++i) line += (i ? " " : "") + std::to_string((int)cfg[i]);
+  line += "\n";
   if (FILE* f = std::fopen(path, "a")) {
-    std::fprintf(f, "%s\t", key.c_str());
-    for (int i = 0; i < 16; ++i) std::fprintf(f, i ? " %d" : "%d", (int)cfg[i]);
-    std::fprintf(f, "\n");
+    std::fwrite(line.data(), 1, line.size(), f);
     std::fclose(f);
   }
 }
