@@ -163,3 +163,13 @@ def test_host_errors():
     plan = tm.Plan(100, 50)
     with pytest.raises(tm.TmfgError):
         tm.build(W=to_dev(np.eye(101, dtype=np.float32)), plan=plan)
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,levels", [(4098, 0), (4099, 0), (4099, 3)])
+def test_selection_split_threshold(n, levels):
+    """Either side of the size from which the exact rule's selection is shared by four waves
+    (more than 128 chunks of 64 faces: n = 4099 has 129 chunks, so three of the four waves
+    cover no chunk), on a random and a tie-heavy matrix, bit-exact against the oracle."""
+    W = synth.random_symmetric(n, n + levels) if levels == 0 else synth.grid_symmetric(n, n, levels=levels)
+    same_tmfg(_build_w(W), oracle.tmfg_lazy(W))
