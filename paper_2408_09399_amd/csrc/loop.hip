@@ -518,6 +518,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ int s_adv;                          // selection's word to the advancing waves: 0 not yet,
                                                  // 1 advance s_u4's rows, 2 nothing to advance
   __shared__ uint64_t s_floor;
+  __shared__ int s_pre;                          // a vertex whose row position is at its first
+                                                 // uninserted entry since the last insertion, or -1
   // paper rule: old keys and new keys of the work items, the best fresh record of the loaded
   // chunks that stays, and the best stale record that was not recomputed
   __shared__ uint64_t s_old[Paper ? kMaxWork : 1], s_newk[Paper ? kMaxWork : 1];
@@ -591,6 +593,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_b0 = 0;
       s_sel.sync = 0;
       s_sel.napp = 0;
+      s_pre = -1;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -621,6 +624,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       s_b0 = 0;
       s_sel.sync = 0;
       s_sel.napp = 0;
+      s_pre = -1;
       if (Paper) {
         s_best0 = 0;
         s_unloaded = 0;
@@ -731,6 +735,18 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       }
     }
     const bool have_cand = s_ins < n;
+    if (wave == kWaves - 1 && have_cand) {
+      // The last wave, before it takes walks, moves the row position of the best fresh
+      // record's vertex (the floor) to its first uninserted entry. That vertex is usually the
+      // next one inserted, and its row is then already advanced when the selection names it:
+      // the vertex's own insertion changes nothing in its row. It is no face corner, so no
+      // walk reads or moves its position meanwhile.
+      const int v = (int)(floor & 0xffffu);
+      if (floor != 0 && floor != ~0ull && v < n && v != s_pre && !is_ins(bits, v)) {
+        advance_row(P.idx, (int)P.ldi, bits, ptr, v, s_m, n, lane);
+        if (lane == 0) s_pre = v;
+      }
+    }
     // Phase B: best pair of every queued face, one group of kGroup lanes per face. A wave
     // takes the next batch of kWave / kGroup faces from a counter when it is free, so a deep
     // walk holds up only its own wave. Batch 0 is the new faces (items [0, nnew)), taken by
@@ -1229,20 +1245,28 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
           }
         }
       }
-    } else if (wave >= kWaves - 4) {
+    } else if (wave >= kWaves - (multi ? 1 : 4)) {
       // The new faces share the new vertex u, whose row no walk has read (a vertex is a face
       // corner only once inserted): its position is 0 while its most similar vertices (its
       // cluster) are mostly inserted already. The new faces' walks, usually the deepest of the
-      // next phase, would each cross that stretch. Once the selection above has named u and
-      // the corners of the face it split (a bounded wait; past the bound nothing is done,
-      // which changes no result), the last four waves move those four rows' positions to
-      // their first uninserted entries, beside the rest of the selection.
+      // next phase, would each cross that stretch. Once the selection above has named u (a
+      // bounded wait; past the bound nothing is done, which changes no result), the last wave
+      // moves u's row position to its first uninserted entry, beside the rest of the
+      // selection, unless the last walk step did so already (no vertex has been inserted
+      // since, and u's own insertion changes nothing in its row). After a single-wave
+      // selection, three more waves do the same for the corners of the face u split; after a
+      // four-wave one that step would end the selection later than it shortens the walks.
       int st = 0;
       for (int it = 0; it < 8192 && st == 0; ++it) {
         st = __hip_atomic_load(&s_adv, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (st == 0) __builtin_amdgcn_s_sleep(1);
       }
-      if (st == 1) advance_row(P.idx, (int)P.ldi, bits, ptr, s_u4[kWaves - 1 - wave], s_m, n, lane);
+      if (st == 1) {
+        const int v = s_u4[kWaves - 1 - wave];
+        if (wave != kWaves - 1 || v != s_pre) advance_row(P.idx, (int)P.ldi, bits, ptr, v, s_m, n, lane);
+        // the word described the bits before this insertion
+        if (wave == kWaves - 1 && lane == 0) s_pre = -1;
+      }
     }
     __syncthreads();
     TMFG_LAP(5);
