@@ -75,6 +75,11 @@ enum {
   /* 32-bit vertex ids (n above 32768). Declared for the interface but not provided: ids and
      face ids are 16-bit throughout, and every call given this flag returns TMFG_E_INVALID. */
   TMFG_IDX32 = 1u << 4,
+  /* Plans: record the insertion loop's counters and step timers (tmfg_plan_stats). They
+     sit on the loop's critical path (counter updates after every face walk, clock reads
+     between the steps of a phase) and cost about a tenth of the loop's time, so a plan made
+     without this flag builds without them; results are the same bits either way. */
+  TMFG_STATS = 1u << 5,
   /* The paper's candidate-limited face rule and heap schedule (Sections 4.1 and 4.2,
      Algorithm 2) instead of the exact greedy rule, for plans and batches. MaxCorrs[v] is
      the most similar uninserted vertex of v (the first uninserted entry of v's sorted row),
@@ -125,9 +130,9 @@ typedef struct {
    area; see tmfg_footprint_bytes). A plan serves one build at a time: builds on one plan
    must be ordered (the same stream, or events), since each one rewrites all of the plan's
    scratch. max_jobs (>= 0) is the most jobs tmfg_build_batch accepts on this plan (0: the
-   plan serves single builds only). Flags: TMFG_NO_VALIDATE, TMFG_TIMING, TMFG_RULE_PAPER or
-   TMFG_RULE_CORR_PREFIX(p) (n_max <= 20480); others, TMFG_IDX32 among them, give
-   TMFG_E_INVALID. */
+   plan serves single builds only). Flags: TMFG_NO_VALIDATE, TMFG_TIMING, TMFG_STATS,
+   TMFG_RULE_PAPER or TMFG_RULE_CORR_PREFIX(p) (n_max <= 20480); others, TMFG_IDX32 among
+   them, give TMFG_E_INVALID. */
 tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, int32_t max_jobs, uint32_t flags);
 
 /* Release a plan and its scratch. Waits for the plan's outstanding work. NULL is a no-op. */
@@ -146,7 +151,8 @@ tmfg_status tmfg_build(tmfg_plan plan, const tmfg_job* job, hipStream_t stream);
    last event. */
 tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]);
 
-/* Counters of the plan's last build (synchronous copy of 32 int32): [0] stale face
+/* Counters of the plan's last build (synchronous copy of 32 int32); TMFG_E_INVALID unless
+   the plan was made with TMFG_STATS. [0] stale face
    recomputes, [1] walk rounds, [2] full-row sweeps, [3] selection phases, [4] walk
    batches, [5..9] microseconds spent in selection, chunk loading, walks, sweeps and
    publishing, [10] microseconds of the whole loop kernel, [11] similarities read from W

@@ -26,6 +26,7 @@ TIMING = 1 << 1
 BATCH_NO_GRAPH = 1 << 2
 BATCH_AUTOTUNE = 1 << 3
 IDX32 = 1 << 4               # declared by the C header; not provided (TMFG_E_INVALID)
+STATS = 1 << 5               # plans: record the insertion loop's counters (Plan.stats)
 RULE_PAPER = 1 << 8
 RULE_CORR = 1 << 9
 PREFIX_SHIFT = 16

@@ -201,7 +201,7 @@ tmfg_status enqueue_build(const Scratch& sc, uint32_t flags, const tmfg_job* job
   P.step_gain = job->step_gain;
   P.faces = job->faces;
   P.status = job->status;
-  P.stats = sc.stats;
+  P.stats = (flags & TMFG_STATS) ? sc.stats : nullptr;   // the loop's counters, when asked for
   P.m = n - 1;
   P.stop_at = INT_MAX;
   P.state = sc.lstate;
@@ -246,7 +246,7 @@ tmfg_status tmfg_plan_create(tmfg_plan* plan, int32_t n_max, int32_t L_max, int3
   bool paper = false;
   int prefix = 0;
   // TMFG_IDX32 (32-bit ids for n above 32768) is declared but not provided
-  if ((flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING | tmfg::kRuleFlags)) ||
+  if ((flags & ~(uint32_t)(TMFG_NO_VALIDATE | TMFG_TIMING | TMFG_STATS | tmfg::kRuleFlags)) ||
       !tmfg::rule_from_flags(flags, &paper, &prefix))
     return TMFG_E_INVALID;
   if (n_max < tmfg::kMinN || n_max > tmfg::kMaxN || L_max < 2 || max_jobs < 0) return TMFG_E_SIZE;
@@ -328,7 +328,7 @@ tmfg_status tmfg_plan_phase_ms(tmfg_plan plan, float ms[5]) {
 }
 
 tmfg_status tmfg_plan_stats(tmfg_plan plan, int32_t out[32]) {
-  if (!plan || !out) return TMFG_E_INVALID;
+  if (!plan || !out || !(plan->flags & TMFG_STATS)) return TMFG_E_INVALID;
   TMFG_HIP(hipMemcpy(out, plan->sc.stats, 128, hipMemcpyDeviceToHost));
   for (int i = 5; i <= 10; ++i) out[i] = (int32_t)((int64_t)out[i] * 1000 / plan->wall_khz);
   for (int i = 16; i < 20; ++i) out[i] = (int32_t)((int64_t)out[i] * 1000 / plan->wall_khz);

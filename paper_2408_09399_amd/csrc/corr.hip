@@ -66,6 +66,9 @@ struct CWork {
 };
 }  // namespace
 
+// Stats records the counters and step timers of tmfg_plan_stats (P.stats is then set); a
+// build that does not ask for them compiles them out.
+template <bool Stats>
 __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   __shared__ CWork work[cMaxWork];
   __shared__ int s_sel[kMaxPrefix];                // the round's chunks, in key order
@@ -119,7 +122,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   if (tid < 9) s_cnt[tid] = P.resume ? hdr->cnt[tid] : 0;
   if (tid == 0) s_t0 = wall_clock64();
 #define CORR_LAP(slot)                    \
-  if (tid == 0) {                         \
+  if (Stats && tid == 0) {                \
     const uint64_t t1_ = wall_clock64();  \
     s_cnt[slot] += t1_ - s_t0;            \
     s_t0 = t1_;                           \
@@ -237,7 +240,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
           }
         }
         __syncthreads();
-        if (tid == 0) s_cnt[0] += (unsigned long long)((s_nwork < cMaxWork ? s_nwork : cMaxWork) - s_listed);
+        if (Stats && tid == 0) s_cnt[0] += (unsigned long long)((s_nwork < cMaxWork ? s_nwork : cMaxWork) - s_listed);
         CORR_LAP(4);
       }
       const int nwork = s_nwork < cMaxWork ? s_nwork : cMaxWork;
@@ -255,7 +258,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
               have_cand ? paper_face<cGroup, cLoads>(P.W, P.idx, n, s_m, (int)P.ldi, bits, ptr, w.a, w.b, w.c, gl, &trips) : 0;
           if (gl == 0) {
             w.best = best;
-            atomicAdd(&s_cnt[1], (unsigned long long)trips);
+            if (Stats) atomicAdd(&s_cnt[1], (unsigned long long)trips);
           }
         }
       }
@@ -353,7 +356,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
     // A1 (wave 0): the p chunks of largest maximum, in key order. The p best pairs lie in them:
     // a pair in any other chunk has p chunk maxima above it.
     if (wave == 0) {
-      if (lane == 0) s_cnt[3] += 1;
+      if (Stats && lane == 0) s_cnt[3] += 1;
       // the lane index is made opaque so that the chunk addresses are formed anew each round
       // rather than held in registers across the whole loop
       int sl_lane = lane;
@@ -493,7 +496,7 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
   __syncthreads();
   if (tid == 0) {
     if (!s_stop) *P.status = 0;
-    if (P.stats) {
+    if (Stats && P.stats) {
       for (int i = 0; i < 32; ++i) P.stats[i] = 0;
       P.stats[0] = (int32_t)(s_cnt[0] > 0x7fffffffull ? 0x7fffffffull : s_cnt[0]);
       P.stats[1] = (int32_t)(s_cnt[1] > 0x7fffffffull ? 0x7fffffffull : s_cnt[1]);
@@ -509,9 +512,10 @@ __device__ void run_corr(const LoopParams& P, uint8_t* smem) {
     publish_outputs(P.hout, P.order, P.edges, P.steps, P.step_gain, P.faces, n, s_stop ? 8 : 0);
 }
 
+template <bool Stats>
 __global__ __launch_bounds__(cBlock) void tmfg_corr_kernel(LoopParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  run_corr(P, smem);
+  run_corr<Stats>(P, smem);
 }
 
 // Batched form: as the lazy loop's, persistent workgroups take instances largest first.
@@ -551,7 +555,7 @@ __global__ __launch_bounds__(cBlock) void batch_corr_kernel(const BatchJob* __re
     P.state = nullptr;
     P.max_rounds = kWalkRounds;
     P.hout = J.hout;
-    run_corr(P, smem);
+    run_corr<false>(P, smem);
     __syncthreads();
   }
 
@@ -560,7 +564,8 @@ __global__ __launch_bounds__(cBlock) void batch_corr_kernel(const BatchJob* __re
 size_t corr_lds_bytes(int n) { return corr_layout(n).total; }
 
 hipError_t corr_init_attributes() {
-  const void* ks[2] = {(const void*)tmfg_corr_kernel, (const void*)batch_corr_kernel};
+  const void* ks[3] = {(const void*)tmfg_corr_kernel<false>, (const void*)tmfg_corr_kernel<true>,
+                       (const void*)batch_corr_kernel};
   for (const void* k : ks) {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, k);
@@ -577,7 +582,10 @@ hipError_t batch_corr_occupancy(int* per_cu, int n_max) {
 }
 
 hipError_t launch_corr(const LoopParams& p, hipStream_t s) {
-  hipLaunchKernelGGL(tmfg_corr_kernel, dim3(1), dim3(cBlock), corr_lds_bytes(p.n), s, p);
+  if (p.stats)
+    hipLaunchKernelGGL(tmfg_corr_kernel<true>, dim3(1), dim3(cBlock), corr_lds_bytes(p.n), s, p);
+  else
+    hipLaunchKernelGGL(tmfg_corr_kernel<false>, dim3(1), dim3(cBlock), corr_lds_bytes(p.n), s, p);
   return hipGetLastError();
 }
 

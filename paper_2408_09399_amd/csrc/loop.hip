@@ -503,7 +503,10 @@ __device__ __forceinline__ uint64_t clock_ticks() { return wall_clock64(); }
 // that was not recomputed; a pair not committed keeps its old record. This is the order in
 // which the heap would pop them. The top record of a phase that finds a stale maximum is
 // always recomputed and committed, so every such phase makes progress.
-template <bool Paper, int CI>
+// Stats records the counters and step timers of tmfg_plan_stats (P.stats is then set); they
+// sit on the loop's critical path (LDS atomics after every walk, clock reads between steps),
+// so a build that does not ask for them compiles them out.
+template <bool Paper, int CI, bool Stats>
 __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ Work work[kMaxWork];
   __shared__ int sel[kMaxSel];
@@ -655,7 +658,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   }
   __syncthreads();
 #define TMFG_LAP(slot)                    \
-  if (tid == 0) {                         \
+  if (Stats && tid == 0) {                \
     const uint64_t t1_ = clock_ticks();   \
     s_cnt[slot] += t1_ - s_t0;            \
     s_t0 = t1_;                           \
@@ -724,7 +727,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (lane == 0) {
       const int done = __hip_atomic_fetch_add(&s_b0, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-      if (done == kWaves - 1) {
+      if (Stats && done == kWaves - 1) {
         const int nw = s_nwork < kMaxWork ? s_nwork : kMaxWork;
         s_cnt[0] += nw - nnew;
         if (s_nwork > kMaxWork) s_cnt[17] += 1;
@@ -776,7 +779,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
       } else if (nnew == 0) {
         continue;
       }
-      if (lane == 0) atomicAdd(&s_cnt[4], 1ull);
+      if (Stats && lane == 0) atomicAdd(&s_cnt[4], 1ull);
       const int item = base + (lane / kGroup);
       if (item < limit) {
         Work& w = work[item];
@@ -791,23 +794,25 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
                            (kWalkDiag && P.stats && gid == 0) ? s_wt : nullptr);
         }
         // per-lane W reads, summed over the group
-        gw = group_sum_i32(gw);
+        if (Stats) gw = group_sum_i32(gw);
         if (gl == 0) {
           w.best = best;
           w.sweep = ok ? 0 : 1;
           if (!ok) atomicAdd(&s_nsweep, 1);
-          atomicMax(&s_bmax, rw);
-          atomicAdd(&s_cnt[1], (unsigned long long)rw);
-          atomicAdd(&s_cnt[11], (unsigned long long)gw);
-          atomicAdd(&s_cnt[15], (unsigned long long)sw);
-          if (rw >= 4) atomicAdd(&s_cnt[13], 1ull);
-          if (rw >= 16) atomicAdd(&s_cnt[14], 1ull);
+          if (Stats) {
+            atomicMax(&s_bmax, rw);
+            atomicAdd(&s_cnt[1], (unsigned long long)rw);
+            atomicAdd(&s_cnt[11], (unsigned long long)gw);
+            atomicAdd(&s_cnt[15], (unsigned long long)sw);
+            if (rw >= 4) atomicAdd(&s_cnt[13], 1ull);
+            if (rw >= 16) atomicAdd(&s_cnt[14], 1ull);
+          }
         }
       }
     }
     __syncthreads();
     const int nwork = s_nwork < kMaxWork ? s_nwork : kMaxWork;
-    if (tid == 0) {
+    if (Stats && tid == 0) {
       s_cnt[12] += s_bmax;
       s_bmax = 0;
     }
@@ -850,7 +855,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         if (old <= lim) {
           // keep the old record: (gain, vertex) back into the item's pair
           work[tid].best = (old & 0xffffffff00000000ull) | (0xffffull - (old & 0xffffull));
-          atomicAdd(&s_cnt[19], 1ull);
+          if (Stats) atomicAdd(&s_cnt[19], 1ull);
         }
       }
       __syncthreads();
@@ -906,7 +911,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     // Phase A: select. For large builds the exact rule spreads the scan of the chunk maxima
     // over kSelWaves waves (below); otherwise, and always for the paper rule (whose choice of
     // stale chunks is ordered), wave 0 selects alone.
-    if (tid == 0) s_cnt[3] += 1;
+    if (Stats && tid == 0) s_cnt[3] += 1;
     // builds of more than two chunk maxima per lane share the scan; smaller ones gain less
     // from it than the waves' exchanges cost
     const bool multi = !Paper && LL.nchunk > 2 * kWave;
@@ -1061,7 +1066,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         // Stale maximum: load every chunk whose maximum is stale and ranks above the best
         // fresh record (the top one first) and recompute their stale records above it.
         if (wave == 0 && lane == 0) {
-          s_cnt[16] += 1;
+          if (Stats) s_cnt[16] += 1;
           sel[0] = c1;
           __hip_atomic_store(&s_adv, 2, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
           s_nsel = 1;
@@ -1222,7 +1227,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         // Stale maximum: load every chunk whose maximum is stale and ranks above the best
         // fresh record (the top one first) and recompute their stale records above it.
         const int c1 = f1 >> 6;
-        if (lane == 0) s_cnt[16] += 1;
+        if (Stats && lane == 0) s_cnt[16] += 1;
         if (lane == 0) sel[0] = c1;
         uint64_t rest = 0;
         const int ns = Paper ? pick_top_stale_chunks(khi, klo, insm, LL.nchunk, kf, c1, c1, sel, 1, sl_lane, &rest)
@@ -1240,7 +1245,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
             work[0] = Work{f1, (int)(r.z & 0xffffu), (int)(r.z >> 16), (int)r.w, 0, 0};
             s_nwork = 1;
             s_nnew = 1;
-            s_cnt[0] += 1;
+            if (Stats) s_cnt[0] += 1;
             s_unloaded = s_rest = rest;
           }
         }
@@ -1284,7 +1289,7 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __syncthreads();
   if (tid == 0) {
     if (!s_stop) *P.status = 0;
-    if (P.stats) {
+    if (Stats && P.stats) {
       for (int i = 0; i < 16; ++i) {
         const unsigned long long v = (i == 10) ? s_tbase + (clock_ticks() - t_start) : s_cnt[i];
         P.stats[i] = (int32_t)(v > 0x7fffffffull ? 0x7fffffffull : v);
@@ -1299,10 +1304,10 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
     publish_outputs(P.hout, P.order, P.edges, P.steps, P.step_gain, P.faces, n, s_stop ? 8 : 0);
 }
 
-template <bool Paper, int CI>
+template <bool Paper, int CI, bool Stats>
 __global__ __launch_bounds__(kBlock) void tmfg_loop_kernel(LoopParams P) {
   extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-  run_loop<Paper, CI>(P, smem);
+  run_loop<Paper, CI, Stats>(P, smem);
 }
 
 // Batched form: persistent workgroups take instances, largest first, from a shared counter;
@@ -1345,7 +1350,7 @@ __global__ __launch_bounds__(kBlock) void batch_loop_kernel(const BatchJob* __re
     P.state = nullptr;
     P.max_rounds = max_rounds;
     P.hout = J.hout;
-    run_loop<Paper, kItersSmall>(P, smem);
+    run_loop<Paper, kItersSmall, false>(P, smem);
     __syncthreads();
   }
 }
@@ -1359,9 +1364,16 @@ hipError_t batch_loop_occupancy(int* per_cu, int n_max, bool paper) {
 }
 
 hipError_t loop_init_attributes() {
-  const void* ks[6] = {(const void*)tmfg_loop_kernel<false, kItersSmall>, (const void*)tmfg_loop_kernel<true, kItersSmall>,
-                       (const void*)tmfg_loop_kernel<false, kItersBig>, (const void*)tmfg_loop_kernel<true, kItersBig>,
-                       (const void*)batch_loop_kernel<false>, (const void*)batch_loop_kernel<true>};
+  const void* ks[10] = {(const void*)tmfg_loop_kernel<false, kItersSmall, false>,
+                        (const void*)tmfg_loop_kernel<true, kItersSmall, false>,
+                        (const void*)tmfg_loop_kernel<false, kItersBig, false>,
+                        (const void*)tmfg_loop_kernel<true, kItersBig, false>,
+                        (const void*)tmfg_loop_kernel<false, kItersSmall, true>,
+                        (const void*)tmfg_loop_kernel<true, kItersSmall, true>,
+                        (const void*)tmfg_loop_kernel<false, kItersBig, true>,
+                        (const void*)tmfg_loop_kernel<true, kItersBig, true>,
+                        (const void*)batch_loop_kernel<false>,
+                        (const void*)batch_loop_kernel<true>};
   for (const void* k : ks) {
     hipFuncAttributes a;
     hipError_t e = hipFuncGetAttributes(&a, k);
@@ -1505,18 +1517,26 @@ hipError_t launch_loop_compacting(LoopParams p, uint16_t* idx, float* vals, hipS
   return e;
 }
 
+template <bool Stats>
+static void launch_loop_as(const LoopParams& p, size_t lds, bool small, hipStream_t s) {
+  if (p.paper && small)
+    hipLaunchKernelGGL((tmfg_loop_kernel<true, kItersSmall, Stats>), dim3(1), dim3(kBlock), lds, s, p);
+  else if (p.paper)
+    hipLaunchKernelGGL((tmfg_loop_kernel<true, kItersBig, Stats>), dim3(1), dim3(kBlock), lds, s, p);
+  else if (small)
+    hipLaunchKernelGGL((tmfg_loop_kernel<false, kItersSmall, Stats>), dim3(1), dim3(kBlock), lds, s, p);
+  else
+    hipLaunchKernelGGL((tmfg_loop_kernel<false, kItersBig, Stats>), dim3(1), dim3(kBlock), lds, s, p);
+}
+
 hipError_t launch_loop(const LoopParams& p, hipStream_t s) {
   const size_t lds = loop_lds_bytes(p.n);
   // the chunk maxima of n vertices fit the smaller register layout up to n = 20480
   const bool small = chunk_iters(p.n) <= kItersSmall;
-  if (p.paper && small)
-    hipLaunchKernelGGL((tmfg_loop_kernel<true, kItersSmall>), dim3(1), dim3(kBlock), lds, s, p);
-  else if (p.paper)
-    hipLaunchKernelGGL((tmfg_loop_kernel<true, kItersBig>), dim3(1), dim3(kBlock), lds, s, p);
-  else if (small)
-    hipLaunchKernelGGL((tmfg_loop_kernel<false, kItersSmall>), dim3(1), dim3(kBlock), lds, s, p);
+  if (p.stats)
+    launch_loop_as<true>(p, lds, small, s);
   else
-    hipLaunchKernelGGL((tmfg_loop_kernel<false, kItersBig>), dim3(1), dim3(kBlock), lds, s, p);
+    launch_loop_as<false>(p, lds, small, s);
   return hipGetLastError();
 }
 

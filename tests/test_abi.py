@@ -215,6 +215,7 @@ def test_noalloc_build_host_side_checks():
 
     assert lib.tmfg_build_noalloc(None, 0, None) == 1
     assert call(job(100), binding.TIMING) == 1
+    assert call(job(100), binding.STATS) == 1                   # plans only
     assert call(job(100), binding.RULE_CORR) == 1               # corr-tmfg needs a prefix
     assert call(job(3)) == 2
     assert call(job(100, L=1, X=True)) == 2

@@ -31,7 +31,7 @@ def test_c3_full_parity():
 def test_c3_paper_rule_parity():
     """The paper's face rule (Algorithm 2) at the same size, against the heap oracle."""
     s = synth.config_c3()
-    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.RULE_PAPER)
+    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.RULE_PAPER | tm.STATS)
     res = tm.build(X=to_dev(s.X), keep_w=True, plan=plan)
     torch.cuda.synchronize()
     got = res.to_numpy()

@@ -41,28 +41,28 @@ def _build(W, plan):
 def test_schedule(n):
     """The library compacts exactly at the documented schedule (none below n = 512)."""
     assert checkpoints(511) == [] and checkpoints(512) == [384] and checkpoints(1000) == [750]
-    _build(synth.random_symmetric(n, 12 + n), tm.Plan(n, 2))
+    _build(synth.random_symmetric(n, 12 + n), tm.Plan(n, 2, tm.STATS))
 
 
 @pytest.mark.parametrize("n", [512, 640, 1000, 1537])
 def test_tie_heavy_exact(n):
     W = synth.grid_symmetric(n, 4000 + n, levels=[2, 4, 8, 16][n % 4])
     print(f"tie-heavy exact n={n}", flush=True)
-    same_tmfg(_build(W, tm.Plan(n, 2)), oracle.tmfg_lazy(W))
+    same_tmfg(_build(W, tm.Plan(n, 2, tm.STATS)), oracle.tmfg_lazy(W))
 
 
 @pytest.mark.parametrize("n", [512, 1000])
 def test_tie_heavy_paper_rule(n):
     W = synth.grid_symmetric(n, 5000 + n, levels=[4, 8][n % 2])
     print(f"tie-heavy paper rule n={n}", flush=True)
-    same_tmfg(_build(W, tm.Plan(n, 2, tm.RULE_PAPER)), oracle.tmfg_paper(W))
+    same_tmfg(_build(W, tm.Plan(n, 2, tm.RULE_PAPER | tm.STATS)), oracle.tmfg_paper(W))
 
 
 @pytest.mark.parametrize("n,p", [(512, 1), (1000, 4), (1537, 16)])
 def test_tie_heavy_corr(n, p):
     W = synth.grid_symmetric(n, 7000 + n, levels=[4, 8, 16][p % 3])
     print(f"tie-heavy corr n={n} p={p}", flush=True)
-    same_tmfg(_build(W, tm.Plan(n, 2, tm.rule_corr_prefix(p))), oracle.tmfg_corr_lazyrows(W, p))
+    same_tmfg(_build(W, tm.Plan(n, 2, tm.rule_corr_prefix(p) | tm.STATS)), oracle.tmfg_corr_lazyrows(W, p))
 
 
 @pytest.mark.parametrize("rule", ["exact", "paper", "corr1", "corr16"])
@@ -74,7 +74,7 @@ def test_clusters_with_noise(rule):
     s = synth.planted_clusters(n, L, sizes, (0.4, 1.0), n_noise=n - sum(sizes), seed=77)
     flags = {"exact": 0, "paper": tm.RULE_PAPER, "corr1": tm.rule_corr_prefix(1),
              "corr16": tm.rule_corr_prefix(16)}[rule]
-    plan = tm.Plan(n, L, flags)
+    plan = tm.Plan(n, L, flags | tm.STATS)
     res = tm.build(X=to_dev(s.X), plan=plan, keep_w=True)
     torch.cuda.synchronize()
     got = res.to_numpy()
@@ -91,7 +91,7 @@ def test_clusters_with_noise(rule):
 def test_plan_reused_across_sizes():
     """One plan, builds of several sizes in a row (with and without checkpoints), each equal
     to the oracle; then the first one again, byte for byte."""
-    plan = tm.Plan(1300, 2)
+    plan = tm.Plan(1300, 2, tm.STATS)
     first = None
     for k, n in enumerate([1300, 300, 777, 1300]):
         W = synth.grid_symmetric(n, 6000 + (n if k < 3 else 1300), levels=4)
@@ -111,7 +111,7 @@ def test_device_error_stops_every_segment(flags):
     compactions of the same launch sequence must leave it stopped, and the plan must then
     build a good matrix correctly."""
     n = 900
-    plan = tm.Plan(n, 2, tm.rule_corr_prefix(4) if flags else 0)
+    plan = tm.Plan(n, 2, (tm.rule_corr_prefix(4) if flags else 0) | tm.STATS)
     W = synth.random_symmetric(n, 31)
     _build(W, plan)                            # leaves the plan's saved state behind
     bad = W.copy()

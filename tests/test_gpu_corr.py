@@ -60,7 +60,7 @@ def test_all_equal_weights():
 @pytest.mark.parametrize("cfg,p", [("config_c1", 1), ("config_c1", 4), ("config_c2", 8)])
 def test_series_path(cfg, p):
     s = getattr(synth, cfg)()
-    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.rule_corr_prefix(p))
+    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.rule_corr_prefix(p) | tm.STATS)
     res = tm.build(X=to_dev(s.X), keep_w=True, plan=plan)
     torch.cuda.synchronize()
     got = res.to_numpy()

@@ -39,7 +39,7 @@ def reference(W, rule):
 @pytest.mark.parametrize("rule", ["exact", "paper", "corr16"])
 def test_max_n(W, rule):
     flags = {"exact": 0, "paper": tm.RULE_PAPER, "corr16": tm.rule_corr_prefix(16)}[rule]
-    plan = tm.Plan(N, 2, flags)
+    plan = tm.Plan(N, 2, flags | tm.STATS)
     print(f"n={N} {rule}: GPU build", flush=True)
     res = tm.build(W=to_dev(W), plan=plan)
     torch.cuda.synchronize()

@@ -59,7 +59,7 @@ _refs = {}
 @pytest.mark.parametrize("rule", ["exact", "paper"])
 def test_n32768_build(big, rule):
     flags = tm.RULE_PAPER if rule == "paper" else 0
-    plan = tm.Plan(N, 64, flags)
+    plan = tm.Plan(N, 64, flags | tm.STATS)
     print(f"n={N} {rule}: GPU build", flush=True)
     res = tm.build(X=to_dev(big), plan=plan, keep_w=True)
     torch.cuda.synchronize()

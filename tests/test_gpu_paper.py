@@ -70,7 +70,7 @@ def test_all_equal_weights():
 @pytest.mark.parametrize("cfg", ["config_c1", "config_c2"])
 def test_series_path(cfg):
     s = getattr(synth, cfg)()
-    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.RULE_PAPER)
+    plan = tm.Plan(s.X.shape[0], s.X.shape[1], tm.RULE_PAPER | tm.STATS)
     res = tm.build(X=to_dev(s.X), keep_w=True, plan=plan)
     torch.cuda.synchronize()
     got = res.to_numpy()
