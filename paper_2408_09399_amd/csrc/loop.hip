@@ -59,6 +59,7 @@ constexpr int kMaxWork = 256;                    // faces recomputed per selecti
 constexpr int kMaxSel = 48;                      // chunks loaded per selection phase
 constexpr int kSelPerWave = kMaxSel / kWaves;    // chunks each wave loads
 constexpr int kSelWaves = 4;                     // waves that share the exact rule's selection
+constexpr int kAdvRow = 16;                      // selection's word kAdvRow + u: advance u's row
 static_assert(kMaxSel % kWaves == 0, "chunks split evenly over the waves");
 static_assert(kMaxWork <= kBlock, "one thread publishes each recomputed face");
 // 64-face chunks of a build and the chunk maxima each lane of a wave covers: the loop is
@@ -516,10 +517,11 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
   __shared__ int s_nwork, s_nnew, s_nsel, s_ins, s_F, s_stop, s_nsweep, s_bmax, s_seed[4], s_next;
   __shared__ int s_b0;                           // waves done with their share of phase B0
   __shared__ SelShare s_sel;                     // the exact rule's selecting waves' posts
-  __shared__ int s_u4[4];                        // the vertex the last selection inserted, and the
-                                                 // corners of the face it split
+  __shared__ int s_u4[4];                        // the vertex the last single-wave selection
+                                                 // inserted, and the corners of the face it split
   __shared__ int s_adv;                          // selection's word to the advancing waves: 0 not yet,
-                                                 // 1 advance s_u4's rows, 2 nothing to advance
+                                                 // 1 advance s_u4's rows, 2 nothing to advance,
+                                                 // kAdvRow + u advance u's row only
   __shared__ uint64_t s_floor;
   __shared__ int s_pre;                          // a vertex whose row position is at its first
                                                  // uninserted entry since the last insertion, or -1
@@ -995,16 +997,15 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         c2 = F >> 6;                             // F is even, so F and F + 1 share a chunk
         ns0 = c2 != c1 ? 2 : 1;
         if (wave == 0) {
+          if (lane == 0) {
+            // first what the advancing wave needs, u itself, in the word that releases it: u's
+            // own row holds no entry of u, so it may be advanced before u's bit is set
+            __hip_atomic_store(&s_adv, kAdvRow + (int)u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            atomicOr(&bits[u >> 5], 1u << (u & 31));
+          }
           const uint4 r = cmax[c1];
           const int x = (int)(r.z & 0xffffu), y = (int)(r.z >> 16), z = (int)r.w;
           if (lane == 0) {
-            // first what the advancing waves need: u's bit and the four rows
-            bits[u >> 5] |= 1u << (u & 31);
-            s_u4[0] = (int)u;
-            s_u4[1] = x;
-            s_u4[2] = y;
-            s_u4[3] = z;
-            __hip_atomic_store(&s_adv, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
             const int st = ins - 4;
             P.order[ins] = (int)u;
             int32_t* e = P.edges + 2 * (6 + 3 * st);
@@ -1266,8 +1267,8 @@ __device__ void run_loop(const LoopParams& P, uint8_t* smem) {
         st = __hip_atomic_load(&s_adv, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (st == 0) __builtin_amdgcn_s_sleep(1);
       }
-      if (st == 1) {
-        const int v = s_u4[kWaves - 1 - wave];
+      if (st == 1 || st >= kAdvRow) {
+        const int v = st == 1 ? s_u4[kWaves - 1 - wave] : st - kAdvRow;
         if (wave != kWaves - 1 || v != s_pre) advance_row(P.idx, (int)P.ldi, bits, ptr, v, s_m, n, lane);
         // the word described the bits before this insertion
         if (wave == kWaves - 1 && lane == 0) s_pre = -1;
