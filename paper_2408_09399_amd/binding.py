@@ -218,6 +218,8 @@ class Plan:
         return tuple(float(x) for x in out)
 
     def stats(self) -> Tuple[int, ...]:
+        """The insertion loop's counters of the last build (tmfg_plan_stats); the plan must have
+        been made with STATS, else TmfgError (TMFG_E_INVALID)."""
         out = (ctypes.c_int32 * 32)()
         _check(_lib().tmfg_plan_stats(self.handle, out), "tmfg_plan_stats")
         return tuple(int(x) for x in out)
