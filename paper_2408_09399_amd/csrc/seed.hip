@@ -40,57 +40,103 @@ __device__ void seed_column(const float* __restrict__ W, int n, double* __restri
   scores[v] = acc;
 }
 
-// Single builds with n a multiple of 4: one thread per row v, adding W[v][u] over u in index
-// order (the definition itself, with no use of symmetry), one wave per 64 rows. Each lane
-// reads its row front to back with 16-byte loads, kSeedDepth blocks of kSeedQuads loads in
-// flight; a load serves one lane, so a wave's load touches 64 lines that the lanes' next
-// loads reuse, and every row is read once, sequentially.
-constexpr int kSeedBlock = 64, kSeedDepth = 4, kSeedQuads = 8;
-static_assert(kSeedDepth * kSeedQuads <= 63, "the loads in flight fit the wave's load counter");
-__global__ __launch_bounds__(kSeedBlock) void seed_rows_kernel(const float* __restrict__ W, int n,
-                                                               double* __restrict__ scores) {
-  const int v = blockIdx.x * kSeedBlock + threadIdx.x;
-  if (v >= n) return;
-  const float4* row = (const float4*)(W + (size_t)v * n);
-  const int nq = n / 4;
-  float4 buf[kSeedDepth][kSeedQuads];
-  // blocks past the row read its last quad (a valid address; the values are never added);
-  // loads are issued whatever the block, so every step has the same count in flight
-  auto issue = [&](int b, float4 (&x)[kSeedQuads]) {
-#pragma unroll
-    for (int k = 0; k < kSeedQuads; ++k) {
-      const int q = b * kSeedQuads + k;
-      x[k] = row[q < nq ? q : nq - 1];
-    }
+// Single builds with n a multiple of 4, tiled: a workgroup of 256 threads owns 64 rows, and
+// all four waves stream those rows through LDS, kSeedCols columns at a time; the 16 threads
+// of a row read its 256-byte span of a tile with one 16-byte load each, so a load
+// instruction covers four rows' contiguous spans (8 lines, where one thread per row, each
+// reading its own row, touches 64). Five register buffers hold four tiles in flight. Lane r of wave 0 then adds row
+// v0 + r of the tile in index order: the sum is the sequential float64 chain of the
+// definition, term by term. The chain is the pace, so a tile that holds no diagonal entry
+// of the workgroup's rows (tile blockIdx.x holds them all) and no column past the row is
+// added with no test per entry: the same additions in the same order.
+constexpr int kSeedRows = 64, kSeedThreads = 256, kSeedCols = 64;
+constexpr int kSeedQ = kSeedCols / 4;                          // quads of a row in a tile
+constexpr int kSeedRowStep = kSeedThreads / kSeedQ;            // rows one pass of loads covers
+static_assert(kSeedRows == kWave && kSeedRows == kSeedCols && kSeedRows / kSeedRowStep == 4,
+              "the layout below");
+#define SEED_ISSUE(t, X)                                                        \
+  do {                                                                          \
+    const int qq_ = (t) * kSeedQ + q;                                           \
+    const int qc_ = qq_ < nq ? qq_ : nq - 1;                                    \
+    X##0 = row0[qc_];                                                           \
+    X##1 = row1[qc_];                                                           \
+    X##2 = row2[qc_];                                                           \
+    X##3 = row3[qc_];                                                           \
+  } while (0)
+#define SEED_STEP(t, XW, XL)                                                    \
+  do {                                                                          \
+    float4(*tb_)[kSeedQ + 1] = tile[(t) & 1];                                   \
+    tb_[r0][q] = XW##0;                                                         \
+    tb_[r0 + kSeedRowStep][q] = XW##1;                                          \
+    tb_[r0 + 2 * kSeedRowStep][q] = XW##2;                                      \
+    tb_[r0 + 3 * kSeedRowStep][q] = XW##3;                                      \
+    SEED_ISSUE((t) + 4, XL);                                                    \
+    __syncthreads();                                                            \
+    if (tid < kSeedRows) {                                                      \
+      if ((t) != (int)blockIdx.x && ((t) + 1) * kSeedCols <= n) {               \
+        _Pragma("unroll") for (int k_ = 0; k_ < kSeedQ; ++k_) {                 \
+          const float4 y_ = tb_[tid][k_];                                       \
+          acc += (double)y_.x;                                                  \
+          acc += (double)y_.y;                                                  \
+          acc += (double)y_.z;                                                  \
+          acc += (double)y_.w;                                                  \
+        }                                                                       \
+      } else {                                                                  \
+        _Pragma("unroll") for (int k_ = 0; k_ < kSeedQ; ++k_) {                 \
+          const float4 y_ = tb_[tid][k_];                                       \
+          const int u_ = (t) * kSeedCols + 4 * k_;                              \
+          const bool in_ = u_ < n;                                              \
+          acc += (!in_ || u_ == v) ? 0.0 : (double)y_.x;                        \
+          acc += (!in_ || u_ + 1 == v) ? 0.0 : (double)y_.y;                    \
+          acc += (!in_ || u_ + 2 == v) ? 0.0 : (double)y_.z;                    \
+          acc += (!in_ || u_ + 3 == v) ? 0.0 : (double)y_.w;                    \
+        }                                                                       \
+      }                                                                         \
+    }                                                                           \
+  } while (0)
+__global__ __launch_bounds__(kSeedThreads) void seed_tiles_kernel(const float* __restrict__ W, int n,
+                                                                  double* __restrict__ scores) {
+  // padded rows: fewer bank conflicts; the buffer tile t goes to was last read two tiles
+  // earlier, before the barrier of the previous tile
+  __shared__ float4 tile[2][kSeedRows][kSeedQ + 1];
+  const int tid = threadIdx.x;
+  const int v0 = blockIdx.x * kSeedRows;
+  const int nq = n / 4, nt = (n + kSeedCols - 1) / kSeedCols;
+  const int q = tid % kSeedQ, r0 = tid / kSeedQ;
+  // rows past n read row n - 1 and quads past the row its last quad (valid addresses; such
+  // values are never added)
+  auto row_of = [&](int r) {
+    const int vr = v0 + r;
+    return (const float4*)(W + (size_t)(vr < n ? vr : n - 1) * n);
   };
+  const float4* row0 = row_of(r0);
+  const float4* row1 = row_of(r0 + kSeedRowStep);
+  const float4* row2 = row_of(r0 + 2 * kSeedRowStep);
+  const float4* row3 = row_of(r0 + 3 * kSeedRowStep);
+  const int v = v0 + tid;                                      // wave 0: the row this lane adds
   double acc = 0.0;
-  auto add = [&](int b, const float4 (&x)[kSeedQuads]) {
-#pragma unroll
-    for (int k = 0; k < kSeedQuads; ++k) {
-      const int u = 4 * (b * kSeedQuads + k);
-      const bool in = u < n;
-      acc += (!in || u == v) ? 0.0 : (double)x[k].x;
-      acc += (!in || u + 1 == v) ? 0.0 : (double)x[k].y;
-      acc += (!in || u + 2 == v) ? 0.0 : (double)x[k].z;
-      acc += (!in || u + 3 == v) ? 0.0 : (double)x[k].w;
-    }
-  };
-  const int nb = (nq + kSeedQuads - 1) / kSeedQuads;
-#pragma unroll
-  for (int d = 0; d < kSeedDepth; ++d) issue(d, buf[d]);
-  int b0 = 0;
-  for (; b0 + kSeedDepth <= nb; b0 += kSeedDepth) {
-#pragma unroll
-    for (int d = 0; d < kSeedDepth; ++d) {
-      add(b0 + d, buf[d]);
-      issue(b0 + d + kSeedDepth, buf[d]);
-    }
+  float4 a0, a1, a2, a3, b0, b1, b2, b3, c0, c1, c2, c3, d0, d1, d2, d3, e0, e1, e2, e3;
+  SEED_ISSUE(0, a);
+  SEED_ISSUE(1, b);
+  SEED_ISSUE(2, c);
+  SEED_ISSUE(3, d);
+  int t0 = 0;
+  for (; t0 + 5 <= nt; t0 += 5) {
+    SEED_STEP(t0, a, e);
+    SEED_STEP(t0 + 1, b, a);
+    SEED_STEP(t0 + 2, c, b);
+    SEED_STEP(t0 + 3, d, c);
+    SEED_STEP(t0 + 4, e, d);
   }
-#pragma unroll
-  for (int d = 0; d < kSeedDepth; ++d)
-    if (b0 + d < nb) add(b0 + d, buf[d]);
-  scores[v] = acc;
+  // the last tiles (conditions uniform over the workgroup)
+  if (t0 < nt) SEED_STEP(t0, a, e);
+  if (t0 + 1 < nt) SEED_STEP(t0 + 1, b, a);
+  if (t0 + 2 < nt) SEED_STEP(t0 + 2, c, b);
+  if (t0 + 3 < nt) SEED_STEP(t0 + 3, d, c);
+  if (tid < kSeedRows && v < n) scores[v] = acc;
 }
+#undef SEED_STEP
+#undef SEED_ISSUE
 
 // Other n: one thread per column (equal to the row: W is bitwise symmetric), adjacent
 // threads on adjacent addresses.
@@ -213,7 +259,7 @@ __global__ __launch_bounds__(256) void batch_validate_kernel(const BatchJob* __r
 
 hipError_t launch_seed_scores(const float* W, int n, double* scores, hipStream_t s) {
   if (n % 4 == 0)
-    hipLaunchKernelGGL(seed_rows_kernel, dim3((n + kSeedBlock - 1) / kSeedBlock), dim3(kSeedBlock), 0, s, W, n,
+    hipLaunchKernelGGL(seed_tiles_kernel, dim3((n + kSeedRows - 1) / kSeedRows), dim3(kSeedThreads), 0, s, W, n,
                        scores);
   else
     hipLaunchKernelGGL(seed_scores_kernel, dim3((n + 255) / 256), dim3(256), 0, s, W, n, scores);
