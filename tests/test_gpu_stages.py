@@ -61,7 +61,9 @@ def test_sort_max_n():
     _sort_check(W, rows=list(rows))
 
 
-@pytest.mark.parametrize("n", [4, 7, 200, 1031, 5000])
+# n a multiple of 4 takes the tiled kernel (64 rows and 64 columns per tile): sizes on and
+# around the tile edges, with the row's end inside a tile or on its edge; others the column kernel
+@pytest.mark.parametrize("n", [4, 7, 8, 60, 64, 68, 128, 200, 1031, 4096, 4100, 5000])
 def test_seed(n):
     W = synth.random_symmetric(n, 1000 + n)
     scores, s4 = tm.seed(to_dev(W))
